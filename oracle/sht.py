@@ -1,0 +1,257 @@
+"""Oracle: the spherical harmonic transform written out from its definition.
+
+TEST INFRASTRUCTURE.  Plain FP64 CPU code (numpy); only the tests, the smoke
+check and the benchmark's CPU-baseline leg use it.  Nothing here is shared
+with the GPU library.
+
+Synthesis (coefficients -> grid) is the regrouped expansion of Section 2,
+equation (alternate_expansion):
+
+    f(theta_i, phi_j) = sum_m e^{i m phi_j} g_m(x_i),
+    g_m(x)            = sum_{k=|m|}^{2l-1} beta_k^m Pbar_k^{|m|}(x),
+
+with x_i the 2l Gauss-Legendre nodes (equation (thetas)).  The sums over k are
+done directly (O(l^3)); the sums over m by a DFT (numpy.fft, or the direct
+sum when asked).
+
+Analysis (grid -> coefficients) is its exact inverse on band-limited data:
+
+    G_m(x_i)  = (1/N) sum_j f(theta_i, phi_j) e^{-i m phi_j},
+    beta_k^m  = sum_i w_i Pbar_k^{|m|}(x_i) G_m(x_i),
+
+exact because the 2l-point Gauss-Legendre rule integrates polynomials of
+degree <= 4l - 1 (products here have degree <= 4l - 2) and the N-point DFT
+separates |m - m'| < N.  The adjoint of synthesis (used by autograd) is the
+same sum without w_i and without 1/N.
+
+Readings where the paper leaves room (each is listed in the design notes):
+
+* phi grid: N = 4l points phi_j = 2 pi j / (4l) ("fft"); the paper's own
+  4l - 1 half-offset points of equation (phis) are available as "paper".
+* Pbar has no Condon-Shortley phase and negative orders use Pbar^{|m|}
+  unchanged (equations (expansion), (association)); hence real fields obey
+  beta_k^{-m} = conj(beta_k^m).
+* Storage order of the coefficients: see ``coeff_index``.
+"""
+import numpy as np
+
+from .legendre import gauss_legendre, pbar_orders
+
+
+# ----------------------------------------------------------------------------------------
+# storage layout (the oracle's own copy; the GPU library has an independent one)
+
+
+def n_coeffs(l, kind="complex"):
+    return 4 * l * l if kind == "complex" else 2 * l * l + l
+
+
+def _order_offset(l, am, kind):
+    """Index of the first entry of order |m| = am in one field's vector."""
+    L2 = 2 * l
+    if kind == "real":
+        return am * L2 - am * (am - 1) // 2
+    if am == 0:
+        return 0
+    return L2 + 2 * (am - 1) * L2 - (am - 1) * am
+
+
+def coeff_index(l, k, m, kind="complex"):
+    """Position of beta_k^m: orders |m| ascending; +m block then -m; k contiguous."""
+    am = abs(m)
+    if not (0 <= am <= k <= 2 * l - 1):
+        raise IndexError("need |m| <= k <= 2l - 1")
+    if kind == "real" and m < 0:
+        raise IndexError("real fields store m >= 0 only")
+    base = _order_offset(l, am, kind)
+    if m < 0:
+        base += 2 * l - am
+    return base + (k - am)
+
+
+def _order_slice(l, m, kind):
+    start = coeff_index(l, abs(m), m, kind)
+    return slice(start, start + 2 * l - abs(m))
+
+
+def phi_points(l, grid="fft"):
+    if grid == "fft":
+        N = 4 * l
+        return 2.0 * np.pi * np.arange(N) / N
+    if grid == "paper":  # equation (phis)
+        N = 4 * l - 1
+        return 2.0 * np.pi * (np.arange(N) + 0.5) / N
+    raise ValueError(grid)
+
+
+def folded_sizes(l, m):
+    """(n_even, n_odd): number of degrees k = m..2l-1 with k - m even / odd."""
+    n = 2 * l - m
+    return (n + 1) // 2, n // 2
+
+
+# ----------------------------------------------------------------------------------------
+# Legendre sums and their inverses
+
+
+def _chunks(seq, size):
+    for s in range(0, len(seq), size):
+        yield seq[s : s + size]
+
+
+def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None):
+    """g[f, m + 2l - 1, i] = sum_k beta_k^m Pbar_k^{|m|}(x_i) for all m.
+
+    For real fields the negative orders are filled in by conjugation.
+    """
+    beta = np.atleast_2d(np.asarray(beta, dtype=np.complex128))
+    F = beta.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    N = len(x)
+    L2 = 2 * l
+    g = np.zeros((F, 2 * L2 - 1, N), dtype=np.complex128)
+    if orders_per_chunk is None:
+        orders_per_chunk = max(1, min(L2, (1 << 24) // max(1, L2 * N)))
+    for ms in _chunks(list(range(L2)), orders_per_chunk):
+        P = pbar_orders(ms, x, L2 - 1)
+        for a, m in enumerate(ms):
+            Pm = P[a, m:, :]  # (degrees, nodes)
+            g[:, m + L2 - 1, :] = beta[:, _order_slice(l, m, kind)] @ Pm
+            if m > 0:
+                if kind == "complex":
+                    g[:, -m + L2 - 1, :] = beta[:, _order_slice(l, -m, kind)] @ Pm
+                else:
+                    g[:, -m + L2 - 1, :] = np.conj(g[:, m + L2 - 1, :])
+    return g
+
+
+def _fourier_sum(g, l, grid, direct):
+    """f[f, i, j] = sum_m g[f, m, i] e^{i m phi_j}."""
+    L2 = 2 * l
+    ms = np.arange(-(L2 - 1), L2)
+    phi = phi_points(l, grid)
+    if grid == "fft" and not direct:
+        N = 4 * l
+        F, _, Ni = g.shape
+        bins = np.zeros((F, Ni, N), dtype=np.complex128)
+        bins[:, :, ms % N] = np.transpose(g, (0, 2, 1))
+        return np.fft.ifft(bins, axis=-1) * N
+    E = np.exp(1j * np.outer(ms, phi))  # (m, j)
+    return np.einsum("fmi,mj->fij", g, E)
+
+
+def _fourier_coeffs(f, l, grid, direct, normalize):
+    """G[f, m + 2l - 1, i] = (1/N)^normalize sum_j f[f, i, j] e^{-i m phi_j}."""
+    L2 = 2 * l
+    ms = np.arange(-(L2 - 1), L2)
+    phi = phi_points(l, grid)
+    N = len(phi)
+    f = np.asarray(f)
+    if grid == "fft" and not direct:
+        G = np.fft.fft(f, axis=-1)[:, :, ms % N]
+    else:
+        E = np.exp(-1j * np.outer(phi, ms))  # (j, m)
+        G = f @ E
+    G = np.transpose(G, (0, 2, 1))
+    if normalize:
+        G = G / N
+    return G
+
+
+def synth(beta, l, kind="complex", grid="fft", direct=False):
+    """Grid values f[field, ring, j] from coefficients beta[field, :] (canonical order)."""
+    x, _ = gauss_legendre(2 * l)
+    g = legendre_sums(beta, l, x, kind)
+    f = _fourier_sum(g, l, grid, direct)
+    return f.real.copy() if kind == "real" else f
+
+
+def ring_values(beta, l, rings, kind="complex", grid="fft", direct=False):
+    """Synthesis restricted to the rings listed (indices into the ascending nodes)."""
+    x, _ = gauss_legendre(2 * l)
+    g = legendre_sums(beta, l, x[np.asarray(rings)], kind)
+    f = _fourier_sum(g, l, grid, direct)
+    return f.real.copy() if kind == "real" else f
+
+
+def _coefficient_sums(G, l, weights, x, kind, orders=None):
+    """beta_k^m = sum_i weights_i Pbar_k^{|m|}(x_i) G[f, m, i] for the orders asked."""
+    F = G.shape[0]
+    L2 = 2 * l
+    out = np.zeros((F, n_coeffs(l, kind)), dtype=np.complex128)
+    aorders = list(range(L2)) if orders is None else sorted({abs(int(m)) for m in orders})
+    chunk = max(1, min(L2, (1 << 24) // max(1, L2 * len(x))))
+    for ms in _chunks(aorders, chunk):
+        P = pbar_orders(ms, x, L2 - 1)
+        for a, m in enumerate(ms):
+            PW = P[a, m:, :] * weights[None, :]  # (degrees, nodes)
+            out[:, _order_slice(l, m, kind)] = G[:, m + L2 - 1, :] @ PW.T
+            if m > 0 and kind == "complex":
+                out[:, _order_slice(l, -m, kind)] = G[:, -m + L2 - 1, :] @ PW.T
+    return out
+
+
+def analyze(f, l, kind="complex", grid="fft", direct=False):
+    """Coefficients (canonical order) from grid values f[field, ring, j]."""
+    f = np.asarray(f)
+    if f.ndim == 2:
+        f = f[None]
+    x, w = gauss_legendre(2 * l)
+    G = _fourier_coeffs(f.astype(np.complex128), l, grid, direct, normalize=True)
+    out = _coefficient_sums(G, l, w, x, kind)
+    if kind == "real":
+        out[:, : 2 * l] = out[:, : 2 * l].real
+    return out
+
+
+def analyze_orders(f, l, orders, kind="complex", grid="fft"):
+    """Analysis for a subset of orders; entries of other orders are left at zero."""
+    f = np.asarray(f)
+    if f.ndim == 2:
+        f = f[None]
+    x, w = gauss_legendre(2 * l)
+    G = _fourier_coeffs(f.astype(np.complex128), l, grid, False, normalize=True)
+    out = _coefficient_sums(G, l, w, x, kind, orders)
+    if kind == "real":
+        out[:, : 2 * l] = out[:, : 2 * l].real
+    return out
+
+
+def synth_adjoint(r, l, kind="complex", grid="fft", direct=False):
+    """Adjoint of ``synth`` for the real inner products of its input and output.
+
+    Complex fields: gamma_k^m = sum_i Pbar_k^{|m|}(x_i) sum_j r_ij e^{-i m phi_j}
+    (the conjugate transpose).  Real fields (m >= 0 stored, beta^{-m} =
+    conj(beta^m)): the same sum times 2 for m > 0, real part only at m = 0.
+    """
+    r = np.asarray(r)
+    if r.ndim == 2:
+        r = r[None]
+    x, _ = gauss_legendre(2 * l)
+    G = _fourier_coeffs(r.astype(np.complex128), l, grid, direct, normalize=False)
+    out = _coefficient_sums(G, l, np.ones_like(x), x, kind)
+    if kind == "real":
+        out *= 2.0
+        out[:, : 2 * l] = 0.5 * out[:, : 2 * l].real
+    return out
+
+
+# ----------------------------------------------------------------------------------------
+# per-order, per-parity matrices on the positive nodes
+
+
+def dense_q(l, m, p):
+    """Q[i, j] = sqrt(2 w_i) Pbar^m_{m+p+2j}(x_i) over the l positive nodes (ascending).
+
+    Columns are orthonormal (orthonormality of Section 2.3 plus parity and the
+    exactness of the Gauss-Legendre rule); this is the analogue on the common
+    grid of the paper's unitary per-order maps (transform), (transform2).
+    """
+    x, w = gauss_legendre(2 * l)
+    xp, wp = x[l:], w[l:]
+    n = folded_sizes(l, m)[p]
+    if n == 0:
+        return np.zeros((l, 0))
+    T = pbar_orders([m], xp, 2 * l - 1)[0]  # (degrees 0..2l-1, nodes)
+    cols = T[m + p : m + p + 2 * n : 2, :].T
+    return np.sqrt(2.0 * wp)[:, None] * cols

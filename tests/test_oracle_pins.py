@@ -1,0 +1,312 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests re-types an oracle formula: each compares the oracle with
+an independent source (a closed form derived by hand from equation
+(association), a library routine, a high-precision evaluation, an identity of
+the functions, a hand-worked grid, or an algebraic property of the maps).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import oracle
+import sht_synthetic as syn
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- Gauss-Legendre grid
+
+
+def test_gl_small_closed_forms():
+    x, w = oracle.gauss_legendre(2)
+    np.testing.assert_allclose(x, [-1 / math.sqrt(3), 1 / math.sqrt(3)], rtol=0, atol=3e-16)
+    np.testing.assert_allclose(w, [1.0, 1.0], rtol=0, atol=1e-15)
+    x, w = oracle.gauss_legendre(3)
+    np.testing.assert_allclose(x, [-math.sqrt(0.6), 0.0, math.sqrt(0.6)], atol=3e-16)
+    np.testing.assert_allclose(w, [5 / 9, 8 / 9, 5 / 9], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 10, 64, 128, 256])
+def test_gl_vs_numpy_leggauss(n):
+    x, w = oracle.gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(x, xr, rtol=0, atol=2e-15)
+    # numpy's own weights carry ~1e-12 relative error at the ends of the interval
+    np.testing.assert_allclose(w, wr, rtol=0, atol=3e-14)
+
+
+def test_gl_vs_mpmath_high_precision():
+    import mpmath as mp
+
+    mp.mp.dps = 40
+    n = 64
+    x, w = oracle.gauss_legendre(n)
+    for i in [0, 1, 2, n // 2, n - 1]:
+        xi = mp.findroot(lambda t: mp.legendre(n, t), mp.mpf(x[i]))
+        dp = mp.diff(lambda t: mp.legendre(n, t), xi)
+        wi = 2 / ((1 - xi ** 2) * dp ** 2)
+        assert abs(x[i] - float(xi)) <= 2.3e-16  # one ulp near 1
+        assert abs(w[i] - float(wi)) <= 2e-13 * float(wi)
+
+
+@pytest.mark.parametrize("n", [512, 2048])
+def test_gl_vs_scipy_roots(n):
+    x, w = oracle.gauss_legendre(n)
+    xr, wr = sps.roots_legendre(n)
+    np.testing.assert_allclose(x, xr, rtol=0, atol=1e-15)
+    # scipy's weights lose ~1e-9 relative accuracy at the ends; compare absolutely
+    np.testing.assert_allclose(w, wr, rtol=0, atol=5e-13)
+    assert np.all(np.diff(x) > 0)  # ascending (equation (thetas) ordering)
+
+
+@pytest.mark.parametrize("l", [4, 32, 128])
+def test_gl_exact_to_degree_4l_minus_1(l):
+    x, w = oracle.gauss_legendre(2 * l)
+    for d in range(0, 4 * l, 1):
+        exact = 0.0 if d % 2 else 2.0 / (d + 1)
+        assert abs(np.sum(w * x ** d) - exact) < 1e-14, d
+
+
+# ---------------------------------------------------------------- Pbar values
+
+
+def test_pbar_closed_forms_low_degree():
+    # From equation (association) by hand: no Condon-Shortley phase.
+    x = np.linspace(-0.97, 0.97, 23)
+    s = np.sqrt(1 - x * x)
+    P = oracle.pbar_orders([0, 1, 2], x, 3)
+    forms = {
+        (0, 0): np.full_like(x, 1 / math.sqrt(2)),
+        (1, 0): math.sqrt(1.5) * x,
+        (1, 1): math.sqrt(3) / 2 * s,
+        (2, 0): math.sqrt(2.5) * (3 * x * x - 1) / 2,
+        (2, 1): math.sqrt(15) / 2 * x * s,
+        (2, 2): math.sqrt(15) / 4 * (1 - x * x),
+        (3, 0): math.sqrt(3.5) * (5 * x ** 3 - 3 * x) / 2,
+    }
+    for (k, m), ref in forms.items():
+        np.testing.assert_allclose(P[m, k], ref, rtol=0, atol=2e-15, err_msg=f"k={k} m={m}")
+    assert np.all(P[0, :, :][[0], :] > 0)
+
+
+def _pbar_scipy(k, m, x):
+    # scipy's lpmv carries the Condon-Shortley factor (-1)^m; the paper's function does not.
+    norm = math.sqrt((2 * k + 1) / 2 * math.exp(math.lgamma(k - m + 1) - math.lgamma(k + m + 1)))
+    return (-1) ** m * norm * sps.lpmv(m, k, x)
+
+
+def test_pbar_vs_scipy_lpmv():
+    x = np.linspace(-0.95, 0.95, 17)
+    K = 30
+    P = oracle.pbar_orders(list(range(K + 1)), x, K)
+    for m in range(0, K + 1):
+        for k in range(m, K + 1):
+            ref = _pbar_scipy(k, m, x)
+            np.testing.assert_allclose(P[m, k], ref, rtol=0, atol=5e-13 * max(1.0, np.max(np.abs(ref))),
+                                       err_msg=f"k={k} m={m}")
+
+
+def _pbar_exact(k, m, x):
+    """Equation (association) evaluated in high precision from the exact power series.
+
+    P_k(x) = 2^-k sum_j (-1)^j C(k, j) C(2k - 2j, k) x^(k - 2j); differentiate m times
+    term by term with exact integers, evaluate with enough digits to survive the
+    cancellation, multiply by the normalization and (1 - x^2)^(m/2).
+    """
+    import mpmath as mp
+
+    mp.mp.dps = int(0.75 * k) + 60
+    xx = mp.mpf(x)
+    total = mp.mpf(0)
+    for j in range(0, k // 2 + 1):
+        e = k - 2 * j
+        if e < m:
+            break
+        coef = (-1) ** j * math.comb(k, j) * math.comb(2 * k - 2 * j, k)
+        coef *= math.factorial(e) // math.factorial(e - m)
+        total += mp.mpf(coef) * xx ** (e - m)
+    total /= mp.mpf(2) ** k
+    norm = mp.sqrt(mp.mpf(2 * k + 1) / 2 * mp.factorial(k - m) / mp.factorial(k + m))
+    return norm * (1 - xx * xx) ** (mp.mpf(m) / 2) * total
+
+
+@pytest.mark.parametrize(
+    "m,x,ks",
+    [
+        (775, 0.924, [775, 1000, 1400, 2047]),  # seed ~1e-323: the underflow band at l = 1024
+        (1500, 0.95, [1500, 2500, 4095]),       # seed far below the FP64 range (l = 2048)
+        (3, 0.3, [3, 500, 2047]),
+    ],
+)
+def test_pbar_vs_exact_series_extreme(m, x, ks):
+    kmax = max(ks)
+    P = oracle.pbar_orders([m], [x], kmax)[0, :, 0]
+    for k in ks:
+        ref = float(_pbar_exact(k, m, x))
+        if abs(ref) < 1e-300:
+            assert abs(P[k] - ref) <= 1e-300
+        else:
+            assert abs(P[k] - ref) <= 1e-12 * abs(ref) + 1e-14, (k, P[k], ref)
+
+
+@pytest.mark.parametrize("x", [0.05, 0.3, 0.924, 0.99, 0.9999])
+def test_unsold_sum_at_high_degree(x):
+    # sum_{m=-k}^{k} Pbar_k^{|m|}(x)^2 = (2k + 1) / 2 for every k (addition theorem).
+    K = 2047
+    P = oracle.pbar_orders(list(range(K + 1)), [x], K)[:, :, 0]  # [m, k]
+    for k in [0, 1, 100, 1023, 1500, 2047]:
+        s = P[0, k] ** 2 + 2 * np.sum(P[1 : k + 1, k] ** 2)
+        assert abs(s - (2 * k + 1) / 2) <= 1e-12 * (2 * k + 1), (k, s)
+
+
+@pytest.mark.parametrize("m", [0, 1, 3, 50, 400])
+def test_step2_recurrence_holds(m):
+    # Lemma rec_relation, equations (recurrence0) and (recurrence) with (c_rec), (d_rec).
+    x = np.linspace(-0.9, 0.9, 11)
+    K = m + 200
+    P = oracle.pbar_orders([m], x, K + 2)[0]
+    ls = np.arange(m, K + 1)
+    c, d = oracle.step2_coefficients(m, ls)
+    cm2, _ = oracle.step2_coefficients(m, ls - 2)
+    for idx, l in enumerate(ls):
+        lhs = x * x * P[l]
+        rhs = d[idx] * P[l] + c[idx] * P[l + 2]
+        if l >= m + 2:
+            rhs = rhs + cm2[idx] * P[l - 2]
+        scale = max(1.0, np.max(np.abs(P[l])))
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13 * scale, err_msg=f"l={l}")
+
+
+def test_step2_closed_values():
+    c, d = oracle.step2_coefficients(0, [0])
+    assert abs(c[0] - 2 / (3 * math.sqrt(5))) < 1e-16
+    assert abs(d[0] - 1 / 3) < 1e-16
+    for m in [0, 4, 17]:
+        _, d = oracle.step2_coefficients(m, [m])
+        assert abs(d[0] - 1 / (2 * m + 3)) < 1e-15
+
+
+@pytest.mark.parametrize("l", [4, 16, 40])
+def test_orthonormal_columns_all_orders(l):
+    for m in range(2 * l):
+        for p in (0, 1):
+            Q = oracle.dense_q(l, m, p)
+            n = Q.shape[1]
+            assert n == oracle.folded_sizes(l, m)[p]
+            if n:
+                np.testing.assert_allclose(Q.T @ Q, np.eye(n), atol=2e-14)
+
+
+@pytest.mark.parametrize("m", [0, 333, 700, 1023])
+def test_orthonormal_columns_l512(m):
+    for p in (0, 1):
+        Q = oracle.dense_q(512, m, p)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=5e-13)
+
+
+# ---------------------------------------------------------------- layout
+
+
+@pytest.mark.parametrize("kind", ["complex", "real"])
+def test_coefficient_layout_matches_generator(kind):
+    for l in [1, 2, 5]:
+        n = oracle.n_coeffs(l, kind)
+        ks = syn.degrees_canonical(l, kind)
+        ms = syn.orders_canonical(l, kind)
+        assert len(ks) == n
+        seen = set()
+        for pos, (k, m) in enumerate(zip(ks, ms)):
+            assert oracle.coeff_index(l, int(k), int(m), kind) == pos
+            seen.add((int(k), int(m)))
+        assert len(seen) == n
+
+
+# ---------------------------------------------------------------- whole transform
+
+
+def test_worked_example_l1():
+    g = json.load(open(os.path.join(HERE, "golden", "l1_worked_example.json")))
+    l = g["l"]
+    x, w = oracle.gauss_legendre(2 * l)
+    np.testing.assert_allclose(x, g["nodes"], atol=3e-16)
+    np.testing.assert_allclose(w, g["weights"], atol=1e-15)
+    for case in g["cases"]:
+        beta = np.zeros((1, oracle.n_coeffs(l)), dtype=complex)
+        beta[0, oracle.coeff_index(l, case["k"], case["m"])] = 1.0
+        ref = np.array(case["grid_re"]) + 1j * np.array(case["grid_im"])
+        for direct in (False, True):
+            f = oracle.synth(beta, l, direct=direct)[0]
+            np.testing.assert_allclose(f, ref, atol=1e-15)
+        back = oracle.analyze(ref[None], l)
+        np.testing.assert_allclose(back, beta, atol=1e-15)
+
+
+def test_against_scipy_spherical_harmonics():
+    # Pbar_k^{|m|}(cos t) e^{i m p} = sqrt(2 pi) (-1)^m Y_k^m(t, p) for m >= 0, and the
+    # conjugate form for m < 0 (scipy's Y carries the Condon-Shortley phase).
+    l = 4
+    beta = syn.coefficients(l, 2, seed=3)
+    f = oracle.synth(beta, l)
+    x, _ = oracle.gauss_legendre(2 * l)
+    theta = np.arccos(x)
+    phi = oracle.phi_points(l)
+    T, PH = np.meshgrid(theta, phi, indexing="ij")
+    ref = np.zeros_like(f)
+    ks, ms = syn.degrees_canonical(l), syn.orders_canonical(l)
+    for pos, (k, m) in enumerate(zip(ks, ms)):
+        am = abs(int(m))
+        Y = sps.sph_harm_y(int(k), am, T, PH)
+        basis = math.sqrt(2 * math.pi) * (-1) ** am * (Y if m >= 0 else np.conj(Y))
+        ref += beta[:, pos][:, None, None] * basis[None]
+    np.testing.assert_allclose(f, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5, 8, 16])
+@pytest.mark.parametrize("kind", ["complex", "real"])
+@pytest.mark.parametrize("grid", ["fft", "paper"])
+def test_round_trip_exact(l, kind, grid):
+    beta = syn.coefficients(l, 3, seed=l, kind=kind)
+    f = oracle.synth(beta, l, kind=kind, grid=grid)
+    if kind == "real":
+        assert np.isrealobj(f)
+    back = oracle.analyze(f, l, kind=kind, grid=grid)
+    np.testing.assert_allclose(back, beta, atol=1e-13 * np.max(np.abs(beta)))
+
+
+@pytest.mark.parametrize("l", [2, 8, 32])
+def test_fft_equals_direct_sum(l):
+    beta = syn.coefficients(l, 2, seed=11)
+    f1 = oracle.synth(beta, l, direct=False)
+    f2 = oracle.synth(beta, l, direct=True)
+    np.testing.assert_allclose(f1, f2, atol=1e-12)
+    np.testing.assert_allclose(oracle.analyze(f1, l, direct=True), oracle.analyze(f1, l), atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["complex", "real"])
+def test_adjoint_identity(kind):
+    # <synth(b), r>_R == <b, synth_adjoint(r)>_R  (real inner products)
+    l = 6
+    b = syn.coefficients(l, 2, seed=5, kind=kind)
+    r = syn.grid(l, 2, seed=6, kind=kind)
+    lhs = np.sum(np.real(np.conj(oracle.synth(b, l, kind=kind)) * r))
+    rhs = np.sum(np.real(np.conj(b) * oracle.synth_adjoint(r, l, kind=kind)))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_subset_routines_agree_with_full():
+    l = 8
+    beta = syn.coefficients(l, 2, seed=9)
+    f = oracle.synth(beta, l)
+    rings = [0, 5, 2 * l - 1]
+    np.testing.assert_allclose(oracle.ring_values(beta, l, rings), f[:, rings], atol=1e-14)
+    full = oracle.analyze(f, l)
+    part = oracle.analyze_orders(f, l, [0, 3, -7])
+    for m in [0, 3, -3, 7, -7]:
+        for k in range(abs(m), 2 * l):
+            i = oracle.coeff_index(l, k, m)
+            assert abs(part[0, i] - full[0, i]) < 1e-14
