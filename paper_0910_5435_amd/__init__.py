@@ -1,0 +1,9 @@
+"""MI355X-native butterfly spherical harmonic transform (Tygert, SHT III).
+
+The compute path lives in ``libsht.so`` (HIP kernels for gfx950 behind a C ABI);
+this package only binds it.  Importing the package does not load the library;
+the first call that needs it does, and raises ImportError if it was not built.
+"""
+from .sht import Butterfly, Plan, coeff_index, gl_nodes, num_coeffs
+
+__all__ = ["Plan", "Butterfly", "coeff_index", "gl_nodes", "num_coeffs"]

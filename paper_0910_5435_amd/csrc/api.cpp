@@ -1,0 +1,416 @@
+// C ABI of the library (declared in include/sht.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "interp_decomp.h"
+#include "sht_internal.h"
+
+namespace sht {
+int build_plan(sht_plan_s* P, const sht_plan_opts& o);
+void free_plan_device(sht_plan_s* P);
+}  // namespace sht
+
+using namespace sht;
+
+struct sht_bf_s {
+  BfTree tree;
+};
+
+namespace {
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Workspace {
+  double* xin;
+  double* v0;
+  double* v1;
+  double* y;
+};
+
+int field_width(const sht_plan_s* P, int F) { return P->kind == SHT_COMPLEX ? 4 * F : 2 * F; }
+
+size_t ws_bytes(const sht_plan_s* P, int F) {
+  const size_t R = static_cast<size_t>(field_width(P, F));
+  return align256(P->rows_in * R * 8) + 2 * align256(P->rows_v * R * 8) +
+         align256(P->rows_y * R * 8);
+}
+
+Workspace carve(const sht_plan_s* P, int F, void* ws) {
+  const size_t R = static_cast<size_t>(field_width(P, F));
+  char* p = static_cast<char*>(ws);
+  Workspace w;
+  w.xin = reinterpret_cast<double*>(p);
+  p += align256(P->rows_in * R * 8);
+  w.v0 = reinterpret_cast<double*>(p);
+  p += align256(P->rows_v * R * 8);
+  w.v1 = reinterpret_cast<double*>(p);
+  p += align256(P->rows_v * R * 8);
+  w.y = reinterpret_cast<double*>(p);
+  return w;
+}
+
+class DeviceScope {
+ public:
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev && dev >= 0) {
+      ok_ = hipSetDevice(dev) == hipSuccess;
+      switched_ = true;
+    }
+  }
+  ~DeviceScope() {
+    if (switched_ && prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = -1;
+  bool switched_ = false;
+  bool ok_ = true;
+};
+
+int check_call(const sht_plan_s* P, int precision, const void* a, const void* b, int F, void* ws,
+               size_t wsb) {
+  if (!P || !a || !b || F < 1 || !ws) return SHT_EINVAL;
+  if (precision != SHT_FP64) return precision == SHT_SPLIT32 || precision == SHT_FP32
+                                        ? SHT_EUNSUPPORTED
+                                        : SHT_EINVAL;
+  if (reinterpret_cast<uintptr_t>(a) % 16 || reinterpret_cast<uintptr_t>(b) % 16) return SHT_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return SHT_EINVAL;
+  if (wsb < ws_bytes(P, F)) return SHT_EINVAL;
+  if (static_cast<long long>(field_width(P, F)) * std::max(P->rows_y, P->rows_in) > (1LL << 40))
+    return SHT_EUNSUPPORTED;
+  return SHT_OK;
+}
+
+#define HIP_OK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return SHT_EHIP; \
+  } while (0)
+
+int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, int F, void* ws,
+              size_t wsb, void* stream) {
+  int rc = check_call(P, precision, coeff, grid, F, ws, wsb);
+  if (rc) return rc;
+  DeviceScope ds(P->device);
+  if (!ds.ok()) return SHT_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int R = field_width(P, F);
+  Workspace w = carve(P, F, ws);
+  HIP_OK(launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
+  HIP_OK(launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
+  for (int t = 1; t <= P->Lmax; ++t) {
+    const double* in = (t - 1) % 2 ? w.v1 : w.v0;
+    double* out = t % 2 ? w.v1 : w.v0;
+    HIP_OK(launch_level(P, t, false, in, out, R, precision, s));
+  }
+  HIP_OK(launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s));
+  HIP_OK(launch_fft_synth(P, w.y, grid, F, R, s));
+  return SHT_OK;
+}
+
+int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coeff, int F, void* ws,
+                   size_t wsb, void* stream, bool adjoint) {
+  int rc = check_call(P, precision, grid, coeff, F, ws, wsb);
+  if (rc) return rc;
+  DeviceScope ds(P->device);
+  if (!ds.ok()) return SHT_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int R = field_width(P, F);
+  Workspace w = carve(P, F, ws);
+  const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);
+  HIP_OK(launch_fft_analyze(P, grid, w.y, F, R, scale, adjoint ? 2.0 : 1.0, s));
+  HIP_OK(launch_final(P, true, nullptr, nullptr, w.v0, w.v1, nullptr, w.y, R, precision, adjoint, s));
+  for (int t = P->Lmax; t >= 1; --t) {
+    const double* in = t % 2 ? w.v1 : w.v0;
+    double* out = (t - 1) % 2 ? w.v1 : w.v0;
+    HIP_OK(launch_level(P, t, true, in, out, R, precision, s));
+  }
+  HIP_OK(launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
+  HIP_OK(launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
+  return SHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sht_default_opts(sht_plan_opts* o) {
+  if (!o) return;
+  o->leaf_width = 64;
+  o->precision = SHT_FP64;
+  o->field_kind = SHT_COMPLEX;
+  o->host_threads = 0;
+  o->device = -1;
+}
+
+int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nullptr, out); }
+
+int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  sht_plan_opts o;
+  sht_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.leaf_width == 0) o.leaf_width = 64;
+  if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 1 || o.leaf_width > 4096)
+    return SHT_EINVAL;
+  if (o.precision < SHT_FP64 || o.precision > SHT_FP32) return SHT_EINVAL;
+  if (o.field_kind != SHT_COMPLEX && o.field_kind != SHT_REAL) return SHT_EINVAL;
+  if (!pow2(l) || l > 2048) return SHT_EUNSUPPORTED;
+  int dev = o.device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return SHT_EHIP;
+  DeviceScope ds(dev);
+  if (!ds.ok()) return SHT_EHIP;
+  sht_plan_s* P = new (std::nothrow) sht_plan_s();
+  if (!P) return SHT_ENOMEM;
+  P->l = l;
+  P->C = o.leaf_width;
+  P->eps = eps;
+  P->device = dev;
+  P->precision = o.precision;
+  P->kind = o.field_kind;
+  int rc;
+  try {
+    rc = build_plan(P, o);
+  } catch (const std::bad_alloc&) {
+    rc = SHT_ENOMEM;
+  } catch (...) {
+    rc = SHT_EINTERNAL;
+  }
+  if (rc != SHT_OK) {
+    free_plan_device(P);
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return SHT_OK;
+}
+
+void sht_destroy(sht_plan_t plan) {
+  if (!plan) return;
+  DeviceScope ds(plan->device);
+  free_plan_device(plan);
+  delete plan;
+}
+
+size_t sht_workspace_bytes(sht_plan_t plan, int nfields, int precision) {
+  if (!plan || nfields < 1 || precision < SHT_FP64 || precision > SHT_FP32) return 0;
+  return ws_bytes(plan, nfields);
+}
+
+int sht_synth(sht_plan_t plan, const double* coeff, double* grid, int F, void* ws, size_t wsb,
+              void* stream) {
+  return plan ? run_synth(plan, plan->precision, coeff, grid, F, ws, wsb, stream) : SHT_EINVAL;
+}
+int sht_analyze(sht_plan_t plan, const double* grid, double* coeff, int F, void* ws, size_t wsb,
+                void* stream) {
+  return plan ? run_transposed(plan, plan->precision, grid, coeff, F, ws, wsb, stream, false)
+              : SHT_EINVAL;
+}
+int sht_synth_adjoint(sht_plan_t plan, const double* grid_cot, double* coeff_cot, int F, void* ws,
+                      size_t wsb, void* stream) {
+  return plan ? run_transposed(plan, plan->precision, grid_cot, coeff_cot, F, ws, wsb, stream, true)
+              : SHT_EINVAL;
+}
+int sht_synth_ex(sht_plan_t plan, int prec, const double* coeff, double* grid, int F, void* ws,
+                 size_t wsb, void* stream) {
+  return run_synth(plan, prec, coeff, grid, F, ws, wsb, stream);
+}
+int sht_analyze_ex(sht_plan_t plan, int prec, const double* grid, double* coeff, int F, void* ws,
+                   size_t wsb, void* stream) {
+  return run_transposed(plan, prec, grid, coeff, F, ws, wsb, stream, false);
+}
+int sht_synth_adjoint_ex(sht_plan_t plan, int prec, const double* grid_cot, double* coeff_cot, int F,
+                         void* ws, size_t wsb, void* stream) {
+  return run_transposed(plan, prec, grid_cot, coeff_cot, F, ws, wsb, stream, true);
+}
+
+int sht_plan_stats(sht_plan_t plan, sht_stats* out) {
+  if (!plan || !out) return SHT_EINVAL;
+  *out = plan->stats;
+  return SHT_OK;
+}
+
+long long sht_num_coeffs(int l, int kind) {
+  if (l < 1) return -1;
+  return kind == SHT_REAL ? 2LL * l * l + l : 4LL * l * l;
+}
+
+long long sht_coeff_index(int l, int k, int m, int kind) {
+  const int am = m < 0 ? -m : m;
+  if (l < 1 || am > k || k > 2 * l - 1) return -1;
+  const long long L2 = 2LL * l;
+  if (kind == SHT_REAL) {
+    if (m < 0) return -1;
+    return static_cast<long long>(am) * L2 - static_cast<long long>(am) * (am - 1) / 2 + (k - am);
+  }
+  long long base = am == 0 ? 0 : L2 + 2LL * (am - 1) * L2 - static_cast<long long>(am - 1) * am;
+  if (m < 0) base += L2 - am;
+  return base + (k - am);
+}
+
+int sht_gl_nodes(int n, double* x, double* w) {
+  if (n < 1 || !x || !w) return SHT_EINVAL;
+  gauss_legendre(n, x, w);
+  return SHT_OK;
+}
+
+int sht_plan_tree(sht_plan_t plan, int m, int p, int* levels, int* n_cols) {
+  if (!plan || m < 0 || m >= 2 * plan->l || (p != 0 && p != 1)) return SHT_EINVAL;
+  if (levels) *levels = plan->levels[2 * m + p];
+  if (n_cols) *n_cols = plan->n_cols[2 * m + p];
+  return SHT_OK;
+}
+
+int sht_plan_columns(sht_plan_t plan, int m, int p, double* q, int ldq) {
+  if (!plan || !q || m < 0 || m >= 2 * plan->l || (p != 0 && p != 1) || ldq < plan->l)
+    return SHT_EINVAL;
+  DeviceScope ds(plan->device);
+  if (!ds.ok()) return SHT_EHIP;
+  const int l = plan->l, C = plan->C, n = plan->n_cols[2 * m + p];
+  if (n == 0) return SHT_OK;
+  const int leaves = (n + C - 1) / C;
+  ColumnBatch cb;
+  cb.npairs = 1;
+  cb.l = l;
+  cb.C = C;
+  std::vector<double> sw(l);
+  for (int i = 0; i < l; ++i) sw[i] = std::sqrt(2.0 * plan->wp[i]);
+  void *dm = nullptr, *dp = nullptr, *dn = nullptr, *dprev = nullptr, *dcur = nullptr,
+       *dexp = nullptr, *dout = nullptr, *dx = nullptr, *dsw = nullptr;
+  int rc = SHT_OK;
+  auto ok = [&](hipError_t e) {
+    if (e != hipSuccess && rc == SHT_OK) rc = SHT_EHIP;
+    return rc == SHT_OK;
+  };
+  if (ok(hipMalloc(&dm, 4)) && ok(hipMalloc(&dp, 4)) && ok(hipMalloc(&dn, 4)) &&
+      ok(hipMalloc(&dprev, 16 * l)) && ok(hipMalloc(&dcur, 16 * l)) && ok(hipMalloc(&dexp, 4 * l)) &&
+      ok(hipMalloc(&dout, 8 * static_cast<size_t>(C) * l)) && ok(hipMalloc(&dx, 8 * l)) &&
+      ok(hipMalloc(&dsw, 8 * l)) && ok(hipMemcpy(dm, &m, 4, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dp, &p, 4, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dn, &n, 4, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dx, plan->xp.data(), 8 * l, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dsw, sw.data(), 8 * l, hipMemcpyHostToDevice))) {
+    cb.d_m = static_cast<int*>(dm);
+    cb.d_p = static_cast<int*>(dp);
+    cb.d_ncols = static_cast<int*>(dn);
+    cb.d_prev = static_cast<double*>(dprev);
+    cb.d_cur = static_cast<double*>(dcur);
+    cb.d_exp = static_cast<int*>(dexp);
+    cb.d_out = static_cast<double*>(dout);
+    cb.d_x = static_cast<const double*>(dx);
+    cb.d_sw = static_cast<const double*>(dsw);
+    std::vector<double> chunk(static_cast<size_t>(C) * l);
+    if (ok(legendre_seed(cb, nullptr))) {
+      for (int c = 0; c < leaves && rc == SHT_OK; ++c) {
+        if (!ok(legendre_chunk(cb, c, nullptr))) break;
+        if (!ok(hipMemcpy(chunk.data(), dout, 8 * chunk.size(), hipMemcpyDeviceToHost))) break;
+        const int width = std::min(C, n - c * C);
+        for (int jj = 0; jj < width; ++jj)
+          std::memcpy(q + static_cast<size_t>(c * C + jj) * ldq, chunk.data() + static_cast<size_t>(jj) * l,
+                      8 * l);
+      }
+    }
+  }
+  for (void* ptr : {dm, dp, dn, dprev, dcur, dexp, dout, dx, dsw})
+    if (ptr) (void)hipFree(ptr);
+  return rc;
+}
+
+// ---- host-only builder -------------------------------------------------------------------
+
+int sht_bf_build(const double* a, int rows, int cols, int lda, int leaf_width, int levels,
+                 double eps, sht_bf_t* out) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  if (rows < 1 || cols < 0 || lda < rows || leaf_width < 1 || !(eps > 0.0) || (!a && cols > 0))
+    return SHT_EINVAL;
+  int L = levels < 0 ? butterfly_depth(cols, leaf_width) : levels;
+  if ((1LL << L) * leaf_width < cols || (1 << L) > rows) return SHT_EINVAL;
+  sht_bf_s* bf = new (std::nothrow) sht_bf_s();
+  if (!bf) return SHT_ENOMEM;
+  try {
+    bf->tree.init(rows, cols, leaf_width, L, eps);
+    for (int c = 0; c < (1 << L); ++c) {
+      const double* chunk = a ? a + static_cast<size_t>(c) * leaf_width * lda : nullptr;
+      if (bf->tree.leaf_width(c) == 0) chunk = a;
+      bf->tree.add_leaf(c, chunk, lda);
+    }
+  } catch (const std::bad_alloc&) {
+    delete bf;
+    return SHT_ENOMEM;
+  } catch (...) {
+    delete bf;
+    return SHT_EINTERNAL;
+  }
+  *out = bf;
+  return SHT_OK;
+}
+
+void sht_bf_destroy(sht_bf_t bf) { delete bf; }
+
+int sht_bf_info(sht_bf_t bf, int* levels, int* k_max, double* k_avg, double* k_sd,
+                long long* factor_entries, long long* m_max_words) {
+  if (!bf) return SHT_EINVAL;
+  const BfTree& t = bf->tree;
+  if (levels) *levels = t.L();
+  if (k_max) *k_max = t.k_max;
+  const double avg = t.n_ids ? t.sum_k / t.n_ids : 0.0;
+  if (k_avg) *k_avg = avg;
+  if (k_sd) *k_sd = t.n_ids ? std::sqrt(std::max(0.0, t.sum_k2 / t.n_ids - avg * avg)) : 0.0;
+  if (factor_entries) *factor_entries = t.factor_entries;
+  if (m_max_words) *m_max_words = t.m_max_words;
+  return SHT_OK;
+}
+
+int sht_bf_block(sht_bf_t bf, int t, int r, int c, int* k, int* K, const int** skel,
+                 const int** red, const double** T) {
+  if (!bf) return SHT_EINVAL;
+  const BfTree& tr = bf->tree;
+  if (t < 0 || t > tr.L() || r < 0 || r >= tr.nrow(t) || c < 0 || c >= tr.ncol(t)) return SHT_EINVAL;
+  const BfBlock& b = tr.block(t, r, c);
+  if (k) *k = b.k;
+  if (K) *K = b.K;
+  if (skel) *skel = b.skel.data();
+  if (red) *red = b.red.data();
+  if (T) *T = b.T.data();
+  return SHT_OK;
+}
+
+int sht_bf_final(sht_bf_t bf, int r, int* row0, int* h, int* k, const double** S, const int** cols) {
+  if (!bf) return SHT_EINVAL;
+  const BfTree& tr = bf->tree;
+  if (r < 0 || r >= (1 << tr.L())) return SHT_EINVAL;
+  const BfFinal& f = tr.final_block(r);
+  if (row0) *row0 = f.row0;
+  if (h) *h = f.h;
+  if (k) *k = f.k;
+  if (S) *S = f.S.data();
+  if (cols) *cols = f.cols.data();
+  return SHT_OK;
+}
+
+const char* sht_strerror(int status) {
+  switch (status) {
+    case SHT_OK: return "success";
+    case SHT_EINVAL: return "invalid argument";
+    case SHT_ENOMEM: return "out of memory";
+    case SHT_EHIP: return "HIP runtime error";
+    case SHT_EUNSUPPORTED: return "unsupported configuration";
+    case SHT_EINTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* sht_version(void) { return "0.1.0"; }
+
+}  // extern "C"

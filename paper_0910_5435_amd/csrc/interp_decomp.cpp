@@ -1,0 +1,270 @@
+// Host FP64 precompute: interpolative decompositions and the depth-first
+// butterfly construction.
+//
+// ID (Section 2.1, Remark QR_algorithm): Householder QR with column pivoting
+// (largest remaining column norm, lowest index on ties).  After k steps
+// A P = Q [R11 R12; 0 R22]; the skeleton is the first k pivots and
+// T = R11^{-1} R12 gives A[:, red] ~= A[:, skel] T with error ||R22||.  The rank
+// is the least k with ||R22||_F <= eps (Remark adaptivity; the rank property of
+// Section 2.2 measures blocks in the Frobenius norm).
+//
+// Butterfly (Section 2.2, equations (1)-(6), (top), (bottom)) built depth-first
+// (Section 3): only the skeleton columns of unprocessed blocks are kept between
+// merges, so a column chunk is needed once and then dropped.
+#include "interp_decomp.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+namespace sht {
+
+void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult& out,
+                   IdWork& w) {
+  out.k = 0;
+  out.skel.clear();
+  out.red.clear();
+  out.T.clear();
+  out.max_abs_t = 0.0;
+  if (n <= 0) return;
+  if (m <= 0) {
+    out.red.resize(n);
+    std::iota(out.red.begin(), out.red.end(), 0);
+    return;
+  }
+  w.a.resize(static_cast<size_t>(m) * n);
+  for (int j = 0; j < n; ++j)
+    std::memcpy(&w.a[static_cast<size_t>(j) * m], A + static_cast<size_t>(j) * lda,
+                sizeof(double) * m);
+  double* a = w.a.data();
+  w.perm.resize(n);
+  std::iota(w.perm.begin(), w.perm.end(), 0);
+  w.nrm.assign(n, 0.0);
+  w.nrm0.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const double* c = a + static_cast<size_t>(j) * m;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += c[i] * c[i];
+    w.nrm[j] = s;
+    w.nrm0[j] = s;
+  }
+  const int kmax = std::min(m, n);
+  const double eps2 = eps * eps;
+  int s = 0;
+  for (; s < kmax; ++s) {
+    double resid = 0.0;
+    int p = s;
+    for (int j = s; j < n; ++j) {
+      resid += w.nrm[j];
+      if (w.nrm[j] > w.nrm[p]) p = j;
+    }
+    if (resid <= eps2) break;
+    if (p != s) {
+      double* cs = a + static_cast<size_t>(s) * m;
+      double* cp = a + static_cast<size_t>(p) * m;
+      for (int i = 0; i < m; ++i) std::swap(cs[i], cp[i]);
+      std::swap(w.perm[s], w.perm[p]);
+      std::swap(w.nrm[s], w.nrm[p]);
+      std::swap(w.nrm0[s], w.nrm0[p]);
+    }
+    // Householder reflector H = I - tau v v^T with v = [1; col[s+1:]] zeroing col[s+1:].
+    double* col = a + static_cast<size_t>(s) * m;
+    const double alpha = col[s];
+    double xn2 = 0.0;
+    for (int i = s + 1; i < m; ++i) xn2 += col[i] * col[i];
+    double tau = 0.0;
+    if (xn2 > 0.0) {
+      const double beta = -std::copysign(std::sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      const double scale = 1.0 / (alpha - beta);
+      for (int i = s + 1; i < m; ++i) col[i] *= scale;
+      col[s] = beta;
+    }
+    for (int j = s + 1; j < n; ++j) {
+      double* cj = a + static_cast<size_t>(j) * m;
+      if (tau != 0.0) {
+        double dot = cj[s];
+        for (int i = s + 1; i < m; ++i) dot += col[i] * cj[i];
+        dot *= tau;
+        cj[s] -= dot;
+        for (int i = s + 1; i < m; ++i) cj[i] -= dot * col[i];
+      }
+      // Downdate the trailing column norm; recompute it exactly once the
+      // downdated value has lost too many digits to cancellation.
+      double nv = w.nrm[j] - cj[s] * cj[s];
+      if (nv < 1e-6 * w.nrm0[j]) {
+        nv = 0.0;
+        for (int i = s + 1; i < m; ++i) nv += cj[i] * cj[i];
+        w.nrm0[j] = nv;
+      }
+      w.nrm[j] = nv;
+    }
+    w.nrm[s] = 0.0;
+  }
+  const int k = s;
+  out.k = k;
+  out.skel.assign(w.perm.begin(), w.perm.begin() + k);
+  out.red.assign(w.perm.begin() + k, w.perm.end());
+  const int nr = n - k;
+  out.T.assign(static_cast<size_t>(k) * nr, 0.0);
+  // T = R11^{-1} R12 by back substitution, one column of R12 at a time.
+  for (int j = 0; j < nr; ++j) {
+    const double* r12 = a + static_cast<size_t>(k + j) * m;
+    double* t = out.T.data() + static_cast<size_t>(j) * k;
+    for (int i = k - 1; i >= 0; --i) {
+      double v = r12[i];
+      for (int q = i + 1; q < k; ++q) v -= a[static_cast<size_t>(q) * m + i] * t[q];
+      t[i] = v / a[static_cast<size_t>(i) * m + i];
+      out.max_abs_t = std::max(out.max_abs_t, std::fabs(t[i]));
+    }
+  }
+}
+
+int butterfly_depth(int cols, int C) {
+  int leaves = (cols + C - 1) / C;
+  int L = 0;
+  while ((1 << L) < leaves) ++L;
+  return L;
+}
+
+void BfTree::init(int rows, int cols, int C, int L, double eps) {
+  if (rows < 0 || cols < 0 || C < 1 || L < 0 || L > 24)
+    throw std::invalid_argument("BfTree::init: bad shape");
+  if ((1 << L) * static_cast<long long>(C) < cols)
+    throw std::invalid_argument("BfTree::init: leaves do not cover the columns");
+  if (rows > 0 && (1 << L) > rows)
+    throw std::invalid_argument("BfTree::init: more row blocks than rows");
+  rows_ = rows;
+  cols_ = cols;
+  C_ = C;
+  L_ = L;
+  eps_ = eps;
+  next_leaf_ = 0;
+  row_lo_.assign(L + 1, {});
+  row_h_.assign(L + 1, {});
+  row_lo_[0] = {0};
+  row_h_[0] = {rows};
+  for (int t = 1; t <= L; ++t) {
+    row_lo_[t].resize(1 << t);
+    row_h_[t].resize(1 << t);
+    for (int q = 0; q < (1 << (t - 1)); ++q) {
+      const int lo = row_lo_[t - 1][q], h = row_h_[t - 1][q];
+      const int top = (h + 1) / 2;
+      row_lo_[t][2 * q] = lo;
+      row_h_[t][2 * q] = top;
+      row_lo_[t][2 * q + 1] = lo + top;
+      row_h_[t][2 * q + 1] = h - top;
+    }
+  }
+  blocks_.assign(L + 1, {});
+  pending_.assign(L + 1, {});
+  for (int t = 0; t <= L; ++t) {
+    blocks_[t].assign(static_cast<size_t>(nrow(t)) * ncol(t), BfBlock{});
+    pending_[t].assign(static_cast<size_t>(nrow(t)) * ncol(t), Pending{});
+  }
+  finals_.assign(1 << L, BfFinal{});
+  k_max = 0;
+  n_ids = 0;
+  sum_k = sum_k2 = 0.0;
+  factor_entries = 0;
+  words_now = m_max_words = 0;
+  max_abs_t = 0.0;
+}
+
+int BfTree::leaf_width(int c) const {
+  long long lo = static_cast<long long>(c) * C_;
+  long long w = std::min<long long>(C_, cols_ - lo);
+  return w > 0 ? static_cast<int>(w) : 0;
+}
+
+void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pending& pend,
+                     const int* gcols) {
+  interp_decomp(a, h, K, lda, eps_, id_, work_);
+  blk.k = id_.k;
+  blk.K = K;
+  blk.skel = id_.skel;
+  blk.red = id_.red;
+  blk.T = id_.T;
+  max_abs_t = std::max(max_abs_t, id_.max_abs_t);
+  factor_entries += static_cast<long long>(blk.T.size());
+  k_max = std::max(k_max, blk.k);
+  n_ids += 1;
+  sum_k += blk.k;
+  sum_k2 += static_cast<double>(blk.k) * blk.k;
+  pend.vals.resize(static_cast<size_t>(h) * blk.k);
+  pend.gcols.resize(blk.k);
+  for (int q = 0; q < blk.k; ++q) {
+    const int src = blk.skel[q];
+    std::memcpy(&pend.vals[static_cast<size_t>(q) * h], a + static_cast<size_t>(src) * lda,
+                sizeof(double) * h);
+    pend.gcols[q] = gcols[src];
+  }
+  pend.live = true;
+  words_now += static_cast<long long>(pend.vals.size());
+}
+
+void BfTree::add_leaf(int c, const double* chunk, int ld) {
+  if (c != next_leaf_) throw std::logic_error("BfTree::add_leaf: leaves must come in order");
+  const int width = leaf_width(c);
+  // the chunk itself is matrix storage held during this step
+  const long long chunk_words = static_cast<long long>(rows_) * width;
+  m_max_words = std::max(m_max_words, words_now + chunk_words);
+  std::vector<int> gcols(width);
+  for (int j = 0; j < width; ++j) gcols[j] = c * C_ + j;
+  id_into(chunk, rows_, width, ld, blocks_[0][c], pending_[0][c], gcols.data());
+  m_max_words = std::max(m_max_words, words_now + chunk_words);
+  ++next_leaf_;
+  // Merge as far as the leaves constructed so far allow (depth-first order).
+  for (int t = 1; t <= L_ && ((c + 1) % (1 << t)) == 0; ++t) merge(t, c >> t);
+  if (complete()) {
+    for (int r = 0; r < (1 << L_); ++r) {
+      Pending& p = pending_[L_][r * ncol(L_) + 0];
+      BfFinal& f = finals_[r];
+      f.row0 = row_lo_[L_][r];
+      f.h = row_h_[L_][r];
+      f.k = blocks_[L_][r].k;
+      f.S = p.vals;
+      f.cols = p.gcols;
+      factor_entries += static_cast<long long>(f.S.size());
+    }
+  }
+}
+
+void BfTree::merge(int t, int cc) {
+  // Blocks (t-1, q, 2cc) | (t-1, q, 2cc+1) on the rows of node q are concatenated
+  // and split into top (2q) and bottom (2q+1) halves; each half is recompressed.
+  for (int q = 0; q < nrow(t - 1); ++q) {
+    const int ncp = ncol(t - 1);
+    Pending& PL = pending_[t - 1][q * ncp + 2 * cc];
+    Pending& PR = pending_[t - 1][q * ncp + 2 * cc + 1];
+    const int h = row_h_[t - 1][q];
+    const int kL = static_cast<int>(PL.gcols.size());
+    const int kR = static_cast<int>(PR.gcols.size());
+    const int K = kL + kR;
+    scratch_.resize(static_cast<size_t>(h) * K);
+    if (kL) std::memcpy(scratch_.data(), PL.vals.data(), sizeof(double) * h * kL);
+    if (kR)
+      std::memcpy(scratch_.data() + static_cast<size_t>(h) * kL, PR.vals.data(),
+                  sizeof(double) * h * kR);
+    std::vector<int> gc(K);
+    for (int j = 0; j < kL; ++j) gc[j] = PL.gcols[j];
+    for (int j = 0; j < kR; ++j) gc[kL + j] = PR.gcols[j];
+    const long long freed = static_cast<long long>(PL.vals.size() + PR.vals.size());
+    for (int half = 0; half < 2; ++half) {
+      const int r = 2 * q + half;
+      const int off = row_lo_[t][r] - row_lo_[t - 1][q];
+      const int hh = row_h_[t][r];
+      id_into(scratch_.data() + off, hh, K, h, blocks_[t][r * ncol(t) + cc],
+              pending_[t][r * ncol(t) + cc], gc.data());
+      m_max_words = std::max(m_max_words, words_now + static_cast<long long>(h) * K);
+    }
+    words_now -= freed;
+    std::vector<double>().swap(PL.vals);
+    std::vector<double>().swap(PR.vals);
+    PL.live = PR.live = false;
+  }
+}
+
+}  // namespace sht

@@ -1,0 +1,408 @@
+// sht_plan: host FP64 precompute of the butterfly factors for every order m and
+// parity p, and their upload in execution order.
+//
+//  1. Gauss-Legendre nodes (equation (thetas)); the l positive ones are the rows
+//     of every Q^{(m,p)}, the diagonal sqrt(2 w) is kept outside the
+//     compressed matrices (Remark omission).
+//  2. Columns of Q^{(m,p)} come from the GPU recurrence kernel one leaf chunk at
+//     a time, and each chunk is consumed at once by the depth-first butterfly
+//     construction (Section 3), so no (m, p) ever holds its full matrix.
+//  3. The resulting IDs are packed step by step (leaves, then each merge level,
+//     then the final skeletons) so the apply kernels stream them in order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "interp_decomp.h"
+#include "sht_internal.h"
+
+namespace sht {
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename F>
+void parallel_for(int n, int nthreads, F&& fn) {
+  if (n <= 0) return;
+  nthreads = std::max(1, std::min(nthreads, n));
+  if (nthreads == 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  th.reserve(nthreads);
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&]() {
+      for (int i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+// Forward declarations of the pieces of plan construction.
+int build_plan(sht_plan_s* P, const sht_plan_opts& o);
+int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees);
+void free_plan_device(sht_plan_s* P);
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return SHT_EHIP;    \
+  } while (0)
+
+int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
+  const double t0 = now_s();
+  const int l = P->l;
+  const int L2 = 2 * l;
+  const int C = P->C;
+  std::vector<double> x(L2), w(L2);
+  gauss_legendre(L2, x.data(), w.data());
+  P->xp.assign(x.begin() + l, x.end());
+  P->wp.assign(w.begin() + l, w.end());
+  const int npairs = 2 * L2;
+  P->n_pairs = npairs;
+  P->n_cols.assign(npairs, 0);
+  P->levels.assign(npairs, 0);
+  int Lmax = 0;
+  for (int m = 0; m < L2; ++m) {
+    const int n = L2 - m;
+    const int n0 = (n + 1) / 2, n1 = n / 2;
+    const int L = butterfly_depth(n0, C);
+    P->n_cols[2 * m] = n0;
+    P->n_cols[2 * m + 1] = n1;
+    P->levels[2 * m] = P->levels[2 * m + 1] = L;
+    Lmax = std::max(Lmax, L);
+  }
+  P->Lmax = Lmax;
+
+  std::vector<BfTree> trees(npairs);
+  for (int mp = 0; mp < npairs; ++mp)
+    trees[mp].init(l, P->n_cols[mp], C, P->levels[mp], P->eps);
+
+  // Device-side column generation, batch by batch.
+  const int nthreads = o.host_threads > 0
+                           ? o.host_threads
+                           : std::max(1u, std::thread::hardware_concurrency());
+  const size_t chunk_doubles = static_cast<size_t>(C) * l;
+  int batch = static_cast<int>(std::max<size_t>(2, (size_t(64) << 20) / (chunk_doubles * 8)));
+  batch = std::min(batch, npairs);
+  batch = std::max(2, batch - (batch % 2));
+
+  DevBuf dx, dsw, dm, dp, dn, dprev, dcur, dexp, dout;
+  HIP_TRY(hipMalloc(&dx.p, sizeof(double) * l));
+  HIP_TRY(hipMalloc(&dsw.p, sizeof(double) * l));
+  std::vector<double> sw(l);
+  for (int i = 0; i < l; ++i) sw[i] = std::sqrt(2.0 * P->wp[i]);
+  HIP_TRY(hipMemcpy(dx.p, P->xp.data(), sizeof(double) * l, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dsw.p, sw.data(), sizeof(double) * l, hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc(&dm.p, sizeof(int) * batch));
+  HIP_TRY(hipMalloc(&dp.p, sizeof(int) * batch));
+  HIP_TRY(hipMalloc(&dn.p, sizeof(int) * batch));
+  HIP_TRY(hipMalloc(&dprev.p, 2 * sizeof(double) * batch * l));  // double-double state
+  HIP_TRY(hipMalloc(&dcur.p, 2 * sizeof(double) * batch * l));
+  HIP_TRY(hipMalloc(&dexp.p, sizeof(int) * batch * l));
+  HIP_TRY(hipMalloc(&dout.p, sizeof(double) * batch * chunk_doubles));
+  double* host_chunk = nullptr;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&host_chunk), sizeof(double) * batch * chunk_doubles));
+  std::unique_ptr<double, void (*)(double*)> host_guard(host_chunk,
+                                                          [](double* q) { (void)hipHostFree(q); });
+
+  double t_cols = 0.0, t_comp = 0.0;
+  int err = SHT_OK;
+  for (int b0 = 0; b0 < npairs && err == SHT_OK; b0 += batch) {
+    const int nb = std::min(batch, npairs - b0);
+    std::vector<int> hm(nb), hp(nb), hn(nb);
+    int leaves = 0;
+    for (int b = 0; b < nb; ++b) {
+      hm[b] = (b0 + b) / 2;
+      hp[b] = (b0 + b) % 2;
+      hn[b] = P->n_cols[b0 + b];
+      leaves = std::max(leaves, 1 << P->levels[b0 + b]);
+    }
+    HIP_TRY(hipMemcpy(dm.p, hm.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dp.p, hp.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dn.p, hn.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+    ColumnBatch cb;
+    cb.npairs = nb;
+    cb.l = l;
+    cb.C = C;
+    cb.d_m = static_cast<int*>(dm.p);
+    cb.d_p = static_cast<int*>(dp.p);
+    cb.d_ncols = static_cast<int*>(dn.p);
+    cb.d_prev = static_cast<double*>(dprev.p);
+    cb.d_cur = static_cast<double*>(dcur.p);
+    cb.d_exp = static_cast<int*>(dexp.p);
+    cb.d_out = static_cast<double*>(dout.p);
+    cb.d_x = static_cast<const double*>(dx.p);
+    cb.d_sw = static_cast<const double*>(dsw.p);
+    HIP_TRY(legendre_seed(cb, nullptr));
+    for (int c = 0; c < leaves; ++c) {
+      double ta = now_s();
+      HIP_TRY(legendre_chunk(cb, c, nullptr));
+      HIP_TRY(hipMemcpy(host_chunk, dout.p, sizeof(double) * nb * chunk_doubles,
+                        hipMemcpyDeviceToHost));
+      double tb = now_s();
+      t_cols += tb - ta;
+      std::atomic<int> bad{0};
+      parallel_for(nb, nthreads, [&](int b) {
+        BfTree& tr = trees[b0 + b];
+        if (c >= (1 << tr.L())) return;
+        try {
+          tr.add_leaf(c, host_chunk + static_cast<size_t>(b) * chunk_doubles, l);
+        } catch (const std::bad_alloc&) {
+          bad = SHT_ENOMEM;
+        } catch (...) {
+          bad = SHT_EINTERNAL;
+        }
+      });
+      t_comp += now_s() - tb;
+      if (bad) {
+        err = bad;
+        break;
+      }
+    }
+  }
+  if (err != SHT_OK) return err;
+
+  // statistics
+  sht_stats& st = P->stats;
+  st.l = l;
+  st.leaf_width = C;
+  st.max_levels = Lmax;
+  st.eps = P->eps;
+  long long nid = 0;
+  double sk = 0, sk2 = 0;
+  int kmax = 0;
+  long long fe = 0, mmax = 0, dense = 0;
+  for (auto& t : trees) {
+    nid += t.n_ids;
+    sk += t.sum_k;
+    sk2 += t.sum_k2;
+    kmax = std::max(kmax, t.k_max);
+    fe += t.factor_entries;
+    mmax = std::max(mmax, t.m_max_words);
+    dense += static_cast<long long>(t.rows()) * t.cols();
+  }
+  st.n_blocks = nid;
+  st.k_max = kmax;
+  st.k_avg = nid ? sk / nid : 0.0;
+  st.k_sd = nid ? std::sqrt(std::max(0.0, sk2 / nid - st.k_avg * st.k_avg)) : 0.0;
+  st.factor_entries = fe;
+  st.dense_entries = dense;
+  st.m_max_words = mmax;
+  st.t_columns_s = t_cols;
+  st.t_compress_s = t_comp;
+  int rc = pack_plan(P, trees);
+  st.t_total_s = now_s() - t0;
+  return rc;
+}
+
+// ------------------------------------------------------------------------------------------
+// packing
+
+int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
+  const int l = P->l;
+  const int L2 = 2 * l;
+  const int npairs = 2 * L2;
+  const int Lmax = P->Lmax;
+  // Row bases: internal coefficient rows and butterfly vector rows per pair.
+  P->in_base.assign(npairs, 0);
+  P->v_base.assign(npairs, 0);
+  P->v_rows.assign(npairs, 0);
+  std::vector<std::vector<std::vector<int>>> voff(npairs);  // [mp][t][block] offsets
+  long long in_rows = 0, v_rows = 0;
+  for (int mp = 0; mp < npairs; ++mp) {
+    P->in_base[mp] = static_cast<int>(in_rows);
+    in_rows += P->n_cols[mp];
+    const BfTree& T = trees[mp];
+    voff[mp].resize(T.L() + 1);
+    int vmax = 0;
+    for (int t = 0; t <= T.L(); ++t) {
+      const int nb = T.nrow(t) * T.ncol(t);
+      voff[mp][t].resize(nb + 1);
+      int acc = 0;
+      for (int b = 0; b < nb; ++b) {
+        voff[mp][t][b] = acc;
+        acc += T.block(t, b / T.ncol(t), b % T.ncol(t)).k;
+      }
+      voff[mp][t][nb] = acc;
+      vmax = std::max(vmax, acc);
+    }
+    P->v_base[mp] = static_cast<int>(v_rows);
+    P->v_rows[mp] = vmax;
+    v_rows += vmax;
+  }
+  if (in_rows > INT32_MAX || v_rows > INT32_MAX) return SHT_EUNSUPPORTED;
+  P->rows_in = in_rows;
+  P->rows_v = v_rows;
+  P->rows_y = static_cast<long long>(L2) * L2;
+
+  std::vector<double> fac;
+  std::vector<uint16_t> idx;
+  std::vector<LevelTask> tasks;
+  std::vector<FinalTask> finals;
+  P->step_off.assign(Lmax + 1, 0);
+  P->step_cnt.assign(Lmax + 1, 0);
+  P->step_maxK.assign(Lmax + 1, 0);
+  P->step_maxk.assign(Lmax + 1, 0);
+  auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off) {
+    idx_off = static_cast<int32_t>(idx.size());
+    for (int v : B.skel) idx.push_back(static_cast<uint16_t>(v));
+    for (int v : B.red) idx.push_back(static_cast<uint16_t>(v));
+    fac_off = static_cast<int64_t>(fac.size());
+    fac.insert(fac.end(), B.T.begin(), B.T.end());
+  };
+  for (int t = 0; t <= Lmax; ++t) {
+    P->step_off[t] = static_cast<long long>(tasks.size());
+    for (int mp = 0; mp < npairs; ++mp) {
+      const BfTree& T = trees[mp];
+      if (T.L() < t) continue;
+      const int vb = P->v_base[mp];
+      if (t == 0) {
+        for (int c = 0; c < T.ncol(0); ++c) {
+          const BfBlock& B = T.block(0, 0, c);
+          if (B.K == 0) continue;
+          LevelTask tk{};
+          tk.in_row = P->in_base[mp] + c * T.C();
+          tk.K = B.K;
+          tk.out_row[0] = vb + voff[mp][0][c];
+          tk.out_row[1] = 0;
+          tk.k[0] = B.k;
+          tk.k[1] = -1;
+          push_block(B, tk.idx[0], tk.fac[0]);
+          tk.idx[1] = 0;
+          tk.fac[1] = 0;
+          tasks.push_back(tk);
+          P->step_maxK[t] = std::max(P->step_maxK[t], B.K);
+          P->step_maxk[t] = std::max(P->step_maxk[t], B.k);
+        }
+      } else {
+        const int ncp = T.ncol(t - 1), nc = T.ncol(t);
+        for (int q = 0; q < T.nrow(t - 1); ++q) {
+          for (int cc = 0; cc < nc; ++cc) {
+            const BfBlock& Bt = T.block(t, 2 * q, cc);
+            const BfBlock& Bb = T.block(t, 2 * q + 1, cc);
+            if (Bt.K == 0) continue;
+            LevelTask tk{};
+            tk.in_row = vb + voff[mp][t - 1][q * ncp + 2 * cc];
+            tk.K = Bt.K;
+            tk.out_row[0] = vb + voff[mp][t][(2 * q) * nc + cc];
+            tk.out_row[1] = vb + voff[mp][t][(2 * q + 1) * nc + cc];
+            tk.k[0] = Bt.k;
+            tk.k[1] = Bb.k;
+            push_block(Bt, tk.idx[0], tk.fac[0]);
+            push_block(Bb, tk.idx[1], tk.fac[1]);
+            tasks.push_back(tk);
+            P->step_maxK[t] = std::max(P->step_maxK[t], Bt.K);
+            P->step_maxk[t] = std::max(P->step_maxk[t], std::max(Bt.k, Bb.k));
+          }
+        }
+      }
+    }
+    P->step_cnt[t] = static_cast<long long>(tasks.size()) - P->step_off[t];
+  }
+  for (int m = 0; m < L2; ++m) {
+    const BfTree& T0 = trees[2 * m];
+    const BfTree& T1 = trees[2 * m + 1];
+    const int L = T0.L();
+    for (int r = 0; r < (1 << L); ++r) {
+      FinalTask ft{};
+      ft.m = m;
+      ft.row0 = T0.row_lo(L, r);
+      ft.h = T0.row_h(L, r);
+      ft.vbuf = L % 2;
+      for (int p = 0; p < 2; ++p) {
+        const BfTree& T = p ? T1 : T0;
+        const BfFinal& f = T.final_block(r);
+        ft.k[p] = f.k;
+        ft.in_row[p] = P->v_base[2 * m + p] + voff[2 * m + p][L][r];
+        ft.fac[p] = static_cast<int64_t>(fac.size());
+        fac.insert(fac.end(), f.S.begin(), f.S.end());
+      }
+      if (ft.h > 0) {
+        finals.push_back(ft);
+        P->final_maxh = std::max(P->final_maxh, ft.h);
+        P->final_maxk = std::max(P->final_maxk, std::max(ft.k[0], ft.k[1]));
+      }
+    }
+  }
+  P->n_final = static_cast<long long>(finals.size());
+  P->n_fac = static_cast<long long>(fac.size());
+  P->n_idx = static_cast<long long>(idx.size());
+  // free host trees early
+  std::vector<BfTree>().swap(trees);
+
+  // device upload
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    if (src) return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return hipSuccess;
+  };
+  std::vector<double> invD(l), D(l);
+  for (int i = 0; i < l; ++i) {
+    D[i] = std::sqrt(2.0 * P->wp[i]);
+    invD[i] = 1.0 / D[i];
+  }
+  const int N = 4 * l;
+  std::vector<double> tw(2 * static_cast<size_t>(N));
+  for (int q = 0; q < N; ++q) {
+    const long double ang = 2.0L * 3.141592653589793238462643383279502884L * q / N;
+    tw[2 * q] = static_cast<double>(cosl(ang));
+    tw[2 * q + 1] = static_cast<double>(sinl(ang));
+  }
+  std::vector<PairDesc> pd(npairs);
+  for (int mp = 0; mp < npairs; ++mp) {
+    pd[mp].m = mp / 2;
+    pd[mp].p = mp % 2;
+    pd[mp].n = P->n_cols[mp];
+    pd[mp].in_base = P->in_base[mp];
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.fac), fac.data(), fac.size() * sizeof(double));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.idx), idx.data(), idx.size() * sizeof(uint16_t));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.tasks), tasks.data(), tasks.size() * sizeof(LevelTask));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.finals), finals.data(), finals.size() * sizeof(FinalTask));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.pairs), pd.data(), pd.size() * sizeof(PairDesc));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.invD), invD.data(), invD.size() * sizeof(double));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.D), D.data(), D.size() * sizeof(double));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.twiddle), tw.data(), tw.size() * sizeof(double));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
+  P->stats.device_bytes =
+      static_cast<long long>(fac.size() * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
+                             finals.size() * sizeof(FinalTask) + pd.size() * sizeof(PairDesc) +
+                             (invD.size() + D.size() + tw.size()) * 8);
+  return SHT_OK;
+}
+
+void free_plan_device(sht_plan_s* P) {
+  void* ptrs[] = {P->d.fac,   P->d.fac_hi, P->d.fac_lo, P->d.idx,    P->d.tasks,
+                  P->d.finals, P->d.pairs, P->d.invD,   P->d.D,      P->d.twiddle};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  P->d = DeviceFactors{};
+}
+
+}  // namespace sht

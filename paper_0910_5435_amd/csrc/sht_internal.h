@@ -1,0 +1,120 @@
+// Internal types shared by the host plan and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sht.h"
+
+namespace sht {
+
+// One butterfly interpolation task: a leaf ID (one output) or a merged pair of
+// row-split IDs that share their input (two outputs, top and bottom; Section
+// 2.2 equations (top), (bottom)).  Rows are indices of R-wide rows in the
+// workspace buffers.  Synthesis reads `in_row` and writes `out_row[]`; the
+// transposed apply reads `out_row[]` and writes `in_row`.
+struct LevelTask {
+  int32_t in_row;     // first row of the input (concatenated children, or leaf columns)
+  int32_t K;          // input length
+  int32_t out_row[2]; // first row of each output block
+  int32_t k[2];       // rank of each output block; k[1] = -1 for a leaf
+  int32_t idx[2];     // offset of [skel (k) | red (K-k)] in the index pool
+  int64_t fac[2];     // offset of T (k x (K-k), column-major) in the factor pool
+};
+
+// Final skeleton product for one order m and one row node r at level L, both
+// parities at once, followed by the parity unfold g(+-x) = E +- O and the row
+// scaling D^{-1} (synthesis) or its transpose (analysis).
+struct FinalTask {
+  int32_t m;
+  int32_t row0, h;    // positive-node rows [row0, row0 + h)
+  int32_t k[2];       // ranks, parity 0 / 1
+  int32_t in_row[2];  // V rows of the level-L blocks, parity 0 / 1
+  int32_t vbuf;       // which V buffer holds them (L % 2)
+  int32_t pad;
+  int64_t fac[2];     // S (h x k, column-major) offsets
+};
+
+// Layout descriptor of one (m, p) pair in the internal coefficient buffer.
+struct PairDesc {
+  int32_t m, p, n;    // order, parity, number of columns n_p
+  int32_t in_base;    // first XIN row
+};
+
+struct DeviceFactors {
+  double* fac = nullptr;       // T and S entries (FP64)
+  float* fac_hi = nullptr;     // FP32 split copies (allocated on first split/fp32 use)
+  float* fac_lo = nullptr;
+  uint16_t* idx = nullptr;     // skel/red index lists
+  LevelTask* tasks = nullptr;  // all level tasks, step by step
+  FinalTask* finals = nullptr;
+  PairDesc* pairs = nullptr;
+  double* invD = nullptr;      // 1 / sqrt(2 w_i) on the positive nodes
+  double* D = nullptr;         // sqrt(2 w_i)
+  double* twiddle = nullptr;   // e^{2 pi i j / N}, j = 0..N-1 (interleaved)
+};
+
+}  // namespace sht
+
+struct sht_plan_s {
+  int l = 0;
+  int C = 64;
+  int Lmax = 0;
+  int device = 0;
+  int precision = SHT_FP64;
+  int kind = SHT_COMPLEX;
+  double eps = 0.0;
+  std::vector<double> xp, wp;           // positive nodes ascending and their weights
+  std::vector<int> n_cols, levels;      // per pair mp = 2m + p
+  std::vector<int> in_base, v_base, v_rows;
+  long long rows_in = 0, rows_v = 0, rows_y = 0;
+  long long n_fac = 0, n_fac_split = 0, n_idx = 0;
+  std::vector<long long> step_off, step_cnt;  // level tasks per step (t = 0..Lmax)
+  std::vector<int> step_maxK, step_maxk;      // largest input / output length per step
+  int final_maxk = 0, final_maxh = 0;
+  long long n_final = 0;
+  long long n_pairs = 0;
+  sht::DeviceFactors d;
+  sht_stats stats{};
+};
+
+namespace sht {
+
+// Kernel launchers (apply.hip, fft.hip, legendre_cols.hip).
+hipError_t launch_coeff_to_xin(const sht_plan_s* P, const double* coeff, double* xin, int F,
+                               int R, hipStream_t s);
+hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* coeff, int F,
+                               int R, hipStream_t s);
+hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in,
+                        double* out, int R, int precision, hipStream_t s);
+hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
+                        double* v0w, double* v1w, double* y, const double* yin, int R,
+                        int precision, bool adjoint, hipStream_t s);
+hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
+                            hipStream_t s);
+hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
+                              double scale, double real_pos, hipStream_t s);
+hipError_t split_factors(sht_plan_s* P, hipStream_t s);
+
+// Legendre column generator (legendre_cols.hip): recurrence state for a batch of pairs.
+struct ColumnBatch {
+  int npairs = 0, l = 0, C = 0;
+  int* d_m = nullptr;
+  int* d_p = nullptr;
+  int* d_ncols = nullptr;
+  double* d_prev = nullptr;    // npairs x l double-double values (2 doubles each)
+  double* d_cur = nullptr;
+  int* d_exp = nullptr;
+  double* d_out = nullptr;     // npairs x C x l
+  const double* d_x = nullptr; // positive nodes (l)
+  const double* d_sw = nullptr;// sqrt(2 w)
+};
+hipError_t legendre_seed(ColumnBatch& b, hipStream_t s);
+hipError_t legendre_chunk(ColumnBatch& b, int chunk, hipStream_t s);
+
+void gauss_legendre(int n, double* x, double* w);
+
+}  // namespace sht

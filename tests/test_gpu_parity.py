@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Error metric: relative l2 over the whole output array of each field; FP64 gate 1e-11.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sht_synthetic as syn
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+
+
+def _plan(l, C=64, eps=1e-13, kind="complex", precision="fp64"):
+    from paper_0910_5435_amd import Plan
+
+    return Plan(l, eps=eps, leaf_width=C, kind=kind, precision=precision)
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    F = a.shape[0]
+    out = []
+    for f in range(F):
+        den = np.linalg.norm(b[f])
+        out.append(np.linalg.norm(a[f] - b[f]) / (den if den > 0 else 1.0))
+    return np.array(out)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# Tolerance on Q entries: the oracle's own step-one recurrence loses ~1e-10 relative on
+# Pbar near x = 1 at degree ~2000 (measured against exact-series values), i.e. ~3e-13
+# after the sqrt(2 w) ~ 2e-3 row factor; at l <= 256 both sides agree to ~1e-14.
+@pytest.mark.parametrize("l,C,orders,tol", [(32, 8, None, 2e-14), (256, 64, [0, 1, 77, 255, 256, 400, 510, 511], 1e-13),
+                                            (1024, 64, [0, 775, 1500, 2047], 1e-12)])
+def test_column_kernel_matches_oracle(l, C, orders, tol):
+    P = _plan(l, C)
+    if orders is None:
+        orders = range(2 * l)
+    worst = 0.0
+    for m in orders:
+        for p in (0, 1):
+            q = P.columns(m, p)
+            ref = oracle.dense_q(l, m, p)
+            assert q.shape == ref.shape
+            if ref.size:
+                err = np.max(np.abs(q - ref))
+                worst = max(worst, err)
+                assert err < tol, (m, p, err)
+    print(f"columns l={l}: max abs diff vs oracle {worst:.3e}")
+
+
+@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5)])
+def test_synth_matches_oracle(l, C, F):
+    P = _plan(l, C)
+    beta = syn.coefficients(l, F, seed=0, power=1.0)
+    ref = oracle.synth(beta, l)
+    got = P.synth(_dev(beta)).cpu().numpy()
+    torch.cuda.synchronize()
+    err = _rel(got, ref)
+    print(f"synth l={l} C={C} F={F} rel_l2 max={err.max():.3e}")
+    assert err.max() < FP64_TOL
+
+
+@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5)])
+def test_analyze_matches_oracle(l, C, F):
+    P = _plan(l, C)
+    g = syn.grid(l, F, seed=1)  # any grid: analysis is a linear map on all of them
+    ref = oracle.analyze(g, l)
+    got = P.analyze(_dev(g)).cpu().numpy()
+    err = _rel(got, ref)
+    print(f"analyze l={l} C={C} F={F} rel_l2 max={err.max():.3e}")
+    assert err.max() < FP64_TOL
+
+
+@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 32, 1)])
+def test_adjoint_matches_oracle(l, C, F):
+    P = _plan(l, C)
+    r = syn.grid(l, F, seed=2)
+    ref = oracle.synth_adjoint(r, l)
+    got = P.synth_adjoint(_dev(r)).cpu().numpy()
+    err = _rel(got, ref)
+    assert err.max() < FP64_TOL
+
+
+@pytest.mark.parametrize("l,C", [(1, 64), (2, 1), (4, 2), (8, 64), (16, 4)])
+def test_tiny_bandlimits(l, C):
+    P = _plan(l, C)
+    beta = syn.coefficients(l, 2, seed=l)
+    ref = oracle.synth(beta, l)
+    got = P.synth(_dev(beta)).cpu().numpy()
+    assert _rel(got, ref).max() < FP64_TOL
+    back = P.analyze(_dev(ref)).cpu().numpy()
+    assert _rel(back, beta).max() < FP64_TOL
+
+
+def test_worked_example_l1_on_gpu():
+    import json, os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    g = json.load(open(os.path.join(here, "golden", "l1_worked_example.json")))
+    P = _plan(1, 64)
+    for case in g["cases"]:
+        beta = np.zeros((1, 4), dtype=complex)
+        beta[0, oracle.coeff_index(1, case["k"], case["m"])] = 1.0
+        ref = np.array(case["grid_re"]) + 1j * np.array(case["grid_im"])
+        got = P.synth(_dev(beta)).cpu().numpy()[0]
+        np.testing.assert_allclose(got, ref, atol=1e-15)
+
+
+@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 64, 1)])
+def test_real_fields(l, C, F):
+    P = _plan(l, C, kind="real")
+    beta = syn.coefficients(l, F, seed=4, kind="real")
+    ref = oracle.synth(beta, l, kind="real")
+    got = P.synth(_dev(beta)).cpu().numpy()
+    assert _rel(got, ref).max() < FP64_TOL
+    back = P.analyze(_dev(ref)).cpu().numpy()
+    assert _rel(back, beta).max() < FP64_TOL
+    r = syn.grid(l, F, seed=5, kind="real")
+    adj = P.synth_adjoint(_dev(r)).cpu().numpy()
+    assert _rel(adj, oracle.synth_adjoint(r, l, kind="real")).max() < FP64_TOL
+
+
+def test_round_trip_gpu_only():
+    l, C, F = 128, 32, 4
+    P = _plan(l, C)
+    beta = _dev(syn.coefficients(l, F, seed=8))
+    back = P.analyze(P.synth(beta))
+    err = _rel(back.cpu().numpy(), beta.cpu().numpy())
+    assert err.max() < FP64_TOL

@@ -1,0 +1,192 @@
+"""CPU tests of the C library: symbols, host precompute (GL nodes, IDs, depth-first
+butterfly), layout helpers and argument validation.  No GPU calls."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import sht_synthetic as syn
+from paper_0910_5435_amd import _lib as L
+from paper_0910_5435_amd import Butterfly, coeff_index, gl_nodes, num_coeffs
+from tests import bf_reference as bfr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "sht.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(sht_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    names = _header_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+        assert n in L.SIGNATURES, f"binding lacks {n}"
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 513, 2048])
+def test_gl_nodes_match_oracle(n):
+    x, w = gl_nodes(n)
+    xo, wo = oracle.gauss_legendre(n)
+    np.testing.assert_allclose(x, xo, rtol=0, atol=3e-16)
+    np.testing.assert_allclose(w, wo, rtol=1e-12, atol=1e-16)
+
+
+@pytest.mark.parametrize("kind", ["complex", "real"])
+@pytest.mark.parametrize("l", [1, 3, 8])
+def test_coeff_index_matches_oracle(kind, l):
+    assert num_coeffs(l, kind) == oracle.n_coeffs(l, kind)
+    for m in range(-(2 * l - 1), 2 * l):
+        for k in range(2 * l):
+            ours = coeff_index(l, k, m, kind)
+            valid = abs(m) <= k and not (kind == "real" and m < 0)
+            if valid:
+                assert ours == oracle.coeff_index(l, k, m, kind)
+            else:
+                assert ours == -1
+
+
+def _depth(n, C):
+    leaves = -(-n // C)
+    L_ = 0
+    while (1 << L_) < leaves:
+        L_ += 1
+    return L_
+
+
+@pytest.mark.parametrize("l,C", [(16, 4), (32, 8), (64, 8), (128, 16)])
+def test_butterfly_matches_dense_q(l, C):
+    eps = 1e-13
+    rng = np.random.default_rng(l)
+    orders = sorted(set([0, 1, l // 2, l - 1, l, 2 * l - 3, 2 * l - 1] + list(rng.integers(0, 2 * l, 4))))
+    for m in orders:
+        n0 = oracle.folded_sizes(l, m)[0]
+        Lm = _depth(n0, C)
+        for p in (0, 1):
+            Q = oracle.dense_q(l, m, p)
+            n = Q.shape[1]
+            bf = Butterfly(Q if n else np.zeros((l, 0)), C, eps, levels=Lm)
+            assert bf.levels == Lm
+            if n == 0:
+                continue
+            X = syn.unit_vectors(n, 5, seed=m)
+            Y = bfr.apply(bf, X)
+            eps_fwd = np.max(np.abs(Y - Q @ X))  # the paper's e_fwd (max abs vs direct)
+            Z = bfr.apply_t(bf, Y)
+            eps_inv = np.max(np.abs(Z - X))  # e_inv: forward then inverse (= transpose)
+            assert eps_fwd < 1e-13, (m, p, eps_fwd)
+            assert eps_inv < 1e-12, (m, p, eps_inv)
+            # transpose of the representation agrees with Q^T on arbitrary vectors
+            V = syn.unit_vectors(l, 3, seed=m + 1)
+            assert np.max(np.abs(bfr.apply_t(bf, V) - Q.T @ V)) < 1e-13
+
+
+def test_id_blocks_are_interpolative():
+    # Every leaf ID reproduces its block: A[:, red] ~= A[:, skel] T within eps (Frobenius),
+    # the skeleton and redundant sets partition the columns, and |T| stays modest
+    # (plain pivoted QR; the paper's algorithm guarantees <= 2).
+    l, C, eps = 128, 16, 1e-12
+    for m in [0, 40, 130]:
+        Q = oracle.dense_q(l, m, 0)
+        n = Q.shape[1]
+        bf = Butterfly(Q, C, eps)
+        for c in range(2 ** bf.levels):
+            skel, red, T = bf.block(0, 0, c)
+            cols = np.arange(c * C, min((c + 1) * C, n))
+            assert sorted(np.concatenate([skel, red]).tolist()) == list(range(len(cols)))
+            A = Q[:, cols]
+            if len(red):
+                err = np.linalg.norm(A[:, red] - A[:, skel] @ T)
+                assert err <= 1.01 * eps + 1e-15
+                assert np.max(np.abs(T)) < 4.0
+            # rank is minimal up to the QR proxy: k never exceeds the numerical rank + slack
+            s = np.linalg.svd(A, compute_uv=False)
+            assert len(skel) <= int(np.sum(s > eps * 1e-3)) + 1
+
+
+def test_figure_multi_structure_8x8():
+    # Figure multi: an 8 x 8 matrix with C = 1 has 4 levels of partitions; every block
+    # holds 8 entries: level t (0-based) has 2^t row blocks of 8/2^t rows.
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((8, 8))
+    bf = Butterfly(A, 1, 1e-14)
+    assert bf.levels == 3
+    for t in range(4):
+        for r in range(2 ** t):
+            for c in range(2 ** (3 - t)):
+                skel, red, T = bf.block(t, r, c)
+                K = len(skel) + len(red)
+                assert K == (1 if t == 0 else None) or t > 0
+                assert len(skel) <= min(8 // 2 ** t, K)
+    rows = sorted((bf.final(r)[0], bf.final(r)[1].shape[0]) for r in range(8))
+    assert rows == [(i, 1) for i in range(8)]
+    # exact when every rank is full (property 5 of Remark QR_algorithm)
+    X = rng.standard_normal((8, 3))
+    np.testing.assert_allclose(bfr.apply(bf, X), A @ X, atol=1e-12)
+    np.testing.assert_allclose(bfr.apply_t(bf, X), A.T @ X, atol=1e-12)
+
+
+def test_depth_first_memory_stays_small():
+    # Section 3: the depth-first traversal holds the current chunk plus the skeleton
+    # columns of unprocessed blocks, far less than the whole matrix.
+    # m_max grows like n log n (Remark on the precomputation trends), so its ratio to
+    # the n^2 words of the matrix falls as n doubles.
+    C = 32
+    ratios = []
+    for l in [256, 512, 1024]:
+        Q = oracle.dense_q(l, 0, 0)
+        bf = Butterfly(Q, C, 1e-13)
+        n = Q.shape[1]
+        assert bf.m_max_words <= l * (C + 2 * (bf.levels + 1) * bf.k_max)
+        ratios.append(bf.m_max_words / (l * n))
+    assert ratios[0] > ratios[1] > ratios[2]
+    assert ratios[2] < 0.5
+
+
+def test_ranks_roughly_independent_of_size():
+    # Remark empirical_rank: with C fixed the average rank barely moves as n doubles.
+    C = 64
+    avgs = []
+    for l in [128, 256, 512]:
+        bf = Butterfly(oracle.dense_q(l, 0, 0), C, 1e-13)
+        avgs.append(bf.k_avg)
+    assert max(avgs) / min(avgs) < 1.35, avgs
+
+
+def test_argument_validation_without_gpu():
+    lib = L.load()
+    h = ctypes.c_void_p()
+    assert lib.sht_plan(3, 1e-13, ctypes.byref(h)) == L.SHT_EUNSUPPORTED
+    assert lib.sht_plan(4096, 1e-13, ctypes.byref(h)) == L.SHT_EUNSUPPORTED
+    assert lib.sht_plan(0, 1e-13, ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_plan(8, 0.0, ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_plan(8, 1.5, ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_plan(8, 1e-13, None) == L.SHT_EINVAL
+    opts = L.PlanOpts()
+    lib.sht_default_opts(ctypes.byref(opts))
+    opts.leaf_width = -2
+    assert lib.sht_plan_ex(8, 1e-13, ctypes.byref(opts), ctypes.byref(h)) == L.SHT_EINVAL
+    opts.leaf_width = 8
+    opts.precision = 7
+    assert lib.sht_plan_ex(8, 1e-13, ctypes.byref(opts), ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_synth(None, None, None, 1, None, 0, None) == L.SHT_EINVAL
+    assert lib.sht_workspace_bytes(None, 1, 0) == 0
+    a = np.zeros((4, 4))
+    bfh = ctypes.c_void_p()
+    assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 2, 1, -1, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
+    assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 4, 1, 5, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
+    assert lib.sht_strerror(L.SHT_EHIP) == b"HIP runtime error"
+    assert lib.sht_version()
