@@ -99,10 +99,12 @@ def _chunks(seq, size):
         yield seq[s : s + size]
 
 
-def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None):
+def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None, orders=None):
     """g[f, m + 2l - 1, i] = sum_k beta_k^m Pbar_k^{|m|}(x_i) for all m.
 
-    For real fields the negative orders are filled in by conjugation.
+    For real fields the negative orders are filled in by conjugation.  With
+    ``orders`` (a list of |m|) only those orders are summed; the others stay 0,
+    i.e. the coefficients of the other orders are treated as zero.
     """
     beta = np.atleast_2d(np.asarray(beta, dtype=np.complex128))
     F = beta.shape[0]
@@ -112,7 +114,8 @@ def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None):
     g = np.zeros((F, 2 * L2 - 1, N), dtype=np.complex128)
     if orders_per_chunk is None:
         orders_per_chunk = max(1, min(L2, (1 << 24) // max(1, L2 * N)))
-    for ms in _chunks(list(range(L2)), orders_per_chunk):
+    aorders = list(range(L2)) if orders is None else sorted({abs(int(m)) for m in orders})
+    for ms in _chunks(aorders, orders_per_chunk):
         P = pbar_orders(ms, x, L2 - 1)
         for a, m in enumerate(ms):
             Pm = P[a, m:, :]  # (degrees, nodes)
@@ -158,10 +161,13 @@ def _fourier_coeffs(f, l, grid, direct, normalize):
     return G
 
 
-def synth(beta, l, kind="complex", grid="fft", direct=False):
-    """Grid values f[field, ring, j] from coefficients beta[field, :] (canonical order)."""
+def synth(beta, l, kind="complex", grid="fft", direct=False, orders=None):
+    """Grid values f[field, ring, j] from coefficients beta[field, :] (canonical order).
+
+    ``orders`` restricts the expansion to the listed |m| (other orders taken as zero).
+    """
     x, _ = gauss_legendre(2 * l)
-    g = legendre_sums(beta, l, x, kind)
+    g = legendre_sums(beta, l, x, kind, orders=orders)
     f = _fourier_sum(g, l, grid, direct)
     return f.real.copy() if kind == "real" else f
 

@@ -89,6 +89,10 @@ SIGNATURES = {
     "sht_bf_block": (_I, [_P, _I, _I, _I, _IP, _IP, ctypes.POINTER(_IP), ctypes.POINTER(_IP),
                           ctypes.POINTER(_DP)]),
     "sht_bf_final": (_I, [_P, _I, _IP, _IP, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_IP)]),
+    "sht_profile_enable": (_I, [_P, _I]),
+    "sht_profile_reset": (_I, [_P]),
+    "sht_profile_count": (_I, [_P]),
+    "sht_profile_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_char_p), _DP, ctypes.POINTER(_LL), _DP, _DP]),
     "sht_strerror": (ctypes.c_char_p, [_I]),
     "sht_version": (ctypes.c_char_p, []),
 }

@@ -22,6 +22,41 @@ struct sht_bf_s {
   BfTree tree;
 };
 
+namespace sht {
+
+int Profiler::find_or_add(const std::string& name, double flops, double bytes) {
+  for (size_t i = 0; i < recs.size(); ++i)
+    if (recs[i].name == name) return static_cast<int>(i);
+  ProfRecord r;
+  r.name = name;
+  r.flops = flops;
+  r.bytes = bytes;
+  recs.push_back(r);
+  return static_cast<int>(recs.size()) - 1;
+}
+
+int Profiler::flush() {
+  int rc = SHT_OK;
+  for (auto& p : pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+      rc = SHT_EHIP;
+    recs[p.rec].ms += ms;
+    recs[p.rec].launches += 1;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pending.clear();
+  return rc;
+}
+
+void Profiler::clear() {
+  (void)flush();
+  recs.clear();
+}
+
+}  // namespace sht
+
 namespace {
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -96,6 +131,54 @@ int check_call(const sht_plan_s* P, int precision, const void* a, const void* b,
     if ((expr) != hipSuccess) return SHT_EHIP; \
   } while (0)
 
+// Algorithmic work of each stage for F fields (flops, HBM bytes per launch).
+struct Work {
+  double flops, bytes;
+};
+
+Work level_work(const sht_plan_s* P, int t, int R) {
+  return {2.0 * P->step_fac[t] * R,
+          8.0 * (P->step_fac[t] + (P->step_rows_in[t] + P->step_rows_out[t]) * R)};
+}
+Work final_work(const sht_plan_s* P, int R) {
+  return {2.0 * P->final_fac * R, 8.0 * (P->final_fac + (P->final_rows_v + P->final_rows_y) * R)};
+}
+Work fft_work(const sht_plan_s* P, int F, int R) {
+  const double N = 4.0 * P->l;
+  const double rows = 2.0 * P->l * F;
+  const double grid_word = P->kind == SHT_COMPLEX ? 16.0 : 8.0;
+  return {5.0 * N * std::log2(N) * rows, 8.0 * P->rows_y * R + rows * N * grid_word};
+}
+Work layout_work(const sht_plan_s* P, int F, int R) {
+  const double ncoef = P->kind == SHT_COMPLEX ? 4.0 * P->l * P->l : 2.0 * P->l * P->l + P->l;
+  return {0.0, 16.0 * ncoef * F + 8.0 * P->rows_in * R};
+}
+
+// Runs one launch; with profiling on, brackets it with events on the stream.
+template <typename Fn>
+int stage(sht_plan_s* P, hipStream_t s, const std::string& name, Work w, Fn&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  int rec = -1;
+  if (P->prof.on) {
+    rec = P->prof.find_or_add(name, w.flops, w.bytes);
+    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) return SHT_EHIP;
+  }
+  if (launch() != hipSuccess) return SHT_EHIP;
+  if (P->prof.on) {
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) return SHT_EHIP;
+    P->prof.pending.push_back({rec, a, b});
+  }
+  return SHT_OK;
+}
+
+#define STAGE(name, work, call)                          \
+  do {                                                   \
+    int _rc = stage(P, s, (name), (work), [&]() { return (call); }); \
+    if (_rc != SHT_OK) return _rc;                       \
+  } while (0)
+
+std::string fsuffix(int F) { return "/F" + std::to_string(F); }
+
 int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, int F, void* ws,
               size_t wsb, void* stream) {
   int rc = check_call(P, precision, coeff, grid, F, ws, wsb);
@@ -105,15 +188,19 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
-  HIP_OK(launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
-  HIP_OK(launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
+  const std::string fs = fsuffix(F);
+  STAGE("synth.layout" + fs, layout_work(P, F, R), launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
+  STAGE("synth.level0" + fs, level_work(P, 0, R),
+        launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
   for (int t = 1; t <= P->Lmax; ++t) {
     const double* in = (t - 1) % 2 ? w.v1 : w.v0;
     double* out = t % 2 ? w.v1 : w.v0;
-    HIP_OK(launch_level(P, t, false, in, out, R, precision, s));
+    STAGE("synth.level" + std::to_string(t) + fs, level_work(P, t, R),
+          launch_level(P, t, false, in, out, R, precision, s));
   }
-  HIP_OK(launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s));
-  HIP_OK(launch_fft_synth(P, w.y, grid, F, R, s));
+  STAGE("synth.final" + fs, final_work(P, R),
+        launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s));
+  STAGE("synth.fft" + fs, fft_work(P, F, R), launch_fft_synth(P, w.y, grid, F, R, s));
   return SHT_OK;
 }
 
@@ -127,15 +214,21 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);
-  HIP_OK(launch_fft_analyze(P, grid, w.y, F, R, scale, adjoint ? 2.0 : 1.0, s));
-  HIP_OK(launch_final(P, true, nullptr, nullptr, w.v0, w.v1, nullptr, w.y, R, precision, adjoint, s));
+  const std::string pre = adjoint ? "adjoint." : "analysis.";
+  const std::string fs = fsuffix(F);
+  STAGE(pre + "fft" + fs, fft_work(P, F, R),
+        launch_fft_analyze(P, grid, w.y, F, R, scale, adjoint ? 2.0 : 1.0, s));
+  STAGE(pre + "final" + fs, final_work(P, R),
+        launch_final(P, true, nullptr, nullptr, w.v0, w.v1, nullptr, w.y, R, precision, adjoint, s));
   for (int t = P->Lmax; t >= 1; --t) {
     const double* in = t % 2 ? w.v1 : w.v0;
     double* out = (t - 1) % 2 ? w.v1 : w.v0;
-    HIP_OK(launch_level(P, t, true, in, out, R, precision, s));
+    STAGE(pre + "level" + std::to_string(t) + fs, level_work(P, t, R),
+          launch_level(P, t, true, in, out, R, precision, s));
   }
-  HIP_OK(launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
-  HIP_OK(launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
+  STAGE(pre + "level0" + fs, level_work(P, 0, R),
+        launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
+  STAGE(pre + "layout" + fs, layout_work(P, F, R), launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
   return SHT_OK;
 }
 
@@ -198,6 +291,7 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
 void sht_destroy(sht_plan_t plan) {
   if (!plan) return;
   DeviceScope ds(plan->device);
+  plan->prof.clear();
   free_plan_device(plan);
   delete plan;
 }
@@ -237,6 +331,41 @@ int sht_synth_adjoint_ex(sht_plan_t plan, int prec, const double* grid_cot, doub
 int sht_plan_stats(sht_plan_t plan, sht_stats* out) {
   if (!plan || !out) return SHT_EINVAL;
   *out = plan->stats;
+  return SHT_OK;
+}
+
+int sht_profile_enable(sht_plan_t plan, int enable) {
+  if (!plan) return SHT_EINVAL;
+  DeviceScope ds(plan->device);
+  if (!enable) (void)plan->prof.flush();
+  plan->prof.on = enable != 0;
+  return SHT_OK;
+}
+
+int sht_profile_reset(sht_plan_t plan) {
+  if (!plan) return SHT_EINVAL;
+  DeviceScope ds(plan->device);
+  plan->prof.clear();
+  return SHT_OK;
+}
+
+int sht_profile_count(sht_plan_t plan) {
+  if (!plan) return SHT_EINVAL;
+  DeviceScope ds(plan->device);
+  const int rc = plan->prof.flush();
+  if (rc != SHT_OK) return rc;
+  return static_cast<int>(plan->prof.recs.size());
+}
+
+int sht_profile_get(sht_plan_t plan, int i, const char** name, double* total_ms,
+                    long long* launches, double* flops_per_launch, double* bytes_per_launch) {
+  if (!plan || i < 0 || i >= static_cast<int>(plan->prof.recs.size())) return SHT_EINVAL;
+  const ProfRecord& r = plan->prof.recs[i];
+  if (name) *name = r.name.c_str();
+  if (total_ms) *total_ms = r.ms;
+  if (launches) *launches = r.launches;
+  if (flops_per_launch) *flops_per_launch = r.flops;
+  if (bytes_per_launch) *bytes_per_launch = r.bytes;
   return SHT_OK;
 }
 

@@ -150,11 +150,12 @@ k_level_trans(const LevelTask* __restrict__ tasks, const double* __restrict__ fa
         dst = skel[q];
         v = w[q * RT + c];
       } else {
+        // T^T stored column-major (nr x k): entry (j, i) at i * nr + j
         const int j = q - k;
+        const int nr = K - k;
         dst = red[j];
-        const double* Tj = T + static_cast<long long>(j) * k;
         v = 0.0;
-        for (int i = 0; i < k; ++i) v = fma(Tj[i], w[i * RT + c], v);
+        for (int i = 0; i < k; ++i) v = fma(T[static_cast<long long>(i) * nr + j], w[i * RT + c], v);
       }
       if (o == 0)
         acc[dst * RT + c] = v;
@@ -247,12 +248,12 @@ k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
         const int q = e / RT, c = e % RT;
         const int p = q < k0 ? 0 : 1;
         const int a = p ? q - k0 : q;
+        // S^T stored column-major (k x h): entry (a, i) at i * k + a
         const int kp = p ? k1 : k0;
-        (void)kp;
-        const double* Sa = (p ? S1 : S0) + static_cast<long long>(a) * h + i0;
+        const double* Sa = (p ? S1 : S0) + static_cast<long long>(i0) * kp + a;
         const double* src = eo[p];
         double v = accv[u];
-        for (int i = 0; i < ih; ++i) v = fma(Sa[i], src[i * RT + c], v);
+        for (int i = 0; i < ih; ++i) v = fma(Sa[static_cast<long long>(i) * kp], src[i * RT + c], v);
         accv[u] = v;
       }
     }
@@ -299,6 +300,7 @@ hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* c
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in, double* out,
                         int R, int precision, hipStream_t s) {
   (void)precision;
+  if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, s);
   const long long cnt = P->step_cnt[step];
   if (cnt == 0) return hipSuccess;
   const LevelTask* tasks = P->d.tasks + P->step_off[step];
@@ -309,7 +311,7 @@ hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const dou
 #define LAUNCH_LEVEL(RTV)                                                                       \
   do {                                                                                           \
     if (transpose)                                                                               \
-      hipLaunchKernelGGL(k_level_trans<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac,      \
+      hipLaunchKernelGGL(k_level_trans<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac_t,    \
                          P->d.idx, in, out, R);                                                  \
     else                                                                                         \
       hipLaunchKernelGGL(k_level_synth<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac,      \
@@ -331,6 +333,9 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
                         int precision, bool adjoint, hipStream_t s) {
   (void)precision;
   if (P->n_final == 0) return hipSuccess;
+  // the transposed MFMA kernel keeps at most 24 row tiles (k0 + k1 <= 384) in registers
+  if (mfma_ok(R) && (!transpose || P->final_maxk <= 192))
+    return launch_final_mfma(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
   const int RT = pick_rt(R, std::max(2LL * P->final_maxk, 64LL * 2));
   dim3 grid(static_cast<unsigned>(P->n_final), R / RT);
   const size_t lds = sizeof(double) * RT * 2 * P->final_maxk;
@@ -339,7 +344,7 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
 #define LAUNCH_FINAL(RTV)                                                                       \
   do {                                                                                           \
     if (transpose)                                                                               \
-      hipLaunchKernelGGL(k_final_trans<RTV>, grid, dim3(kThreads), 0, s, P->d.finals, P->d.fac,  \
+      hipLaunchKernelGGL(k_final_trans<RTV>, grid, dim3(kThreads), 0, s, P->d.finals, P->d.fac_t,\
                          yin, scale, half, v0w, v1w, P->l, R);                                   \
     else                                                                                         \
       hipLaunchKernelGGL(k_final_synth<RTV>, grid, dim3(kThreads), lds, s, P->d.finals,          \

@@ -1,11 +1,14 @@
 // Longitude sums by FFT (Section 2: the sums over m of equation
 // (alternate_expansion) are discrete Fourier transforms).  One work-group owns one
-// (field, ring) row of N = 4l points, held in LDS; radix-2 decimation in time after a
-// bit-reversed load.  FP64 throughout.
+// (field, ring) row of N = 4l points, held in LDS; decimation in time after a
+// bit-reversed load, two radix-2 stages per LDS pass (each thread owns a closed set of
+// four points), FP64 throughout.
 //
 // Synthesis reads the Legendre output Y[m][ring][R] (bins +m and -m = N - m) and writes
 // the grid row; analysis reads a grid row and writes the bins back in the same layout,
-// scaled by 1/N (analysis) or 1 (adjoint).
+// scaled by 1/N (analysis) or 1 (adjoint).  A Y row holds all fields of one (m, ring),
+// so work-groups are numbered field-fastest within each XCD: the groups of one ring run
+// together on one XCD and share the L2 lines of their Y gathers and scatters.
 #include "sht_internal.h"
 
 namespace sht {
@@ -13,58 +16,94 @@ namespace sht {
 namespace {
 
 constexpr int kFftThreads = 256;
+constexpr int kXcd = 8;
 
-__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) {
-  return __brev(v) >> (32 - bits);
+__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
+
+__device__ __forceinline__ double2 cmul(double2 a, double wr, double wi) {
+  return make_double2(a.x * wr - a.y * wi, a.x * wi + a.y * wr);
 }
 
-// In-place radix-2 DIT on bit-reversed input; sign +1 uses e^{+i}, -1 uses e^{-i}.
+// In-place DIT on bit-reversed input; sign +1 uses e^{+i}, -1 uses e^{-i}.
 __device__ void fft_lds(double2* X, int N, int logN, const double* __restrict__ tw, double sign) {
-  for (int s = 0; s < logN; ++s) {
-    const int half = 1 << s;
-    const int stride = N >> (s + 1);  // twiddle index step
+  int s = 0;
+  for (; s + 1 < logN; s += 2) {
+    const int h = 1 << s;
+    __syncthreads();
+    for (int b = threadIdx.x; b < N / 4; b += kFftThreads) {
+      const int pos = b & (h - 1);
+      const int i0 = ((b >> s) << (s + 2)) + pos;
+      // stage s: pairs (i0, i0+h), (i0+2h, i0+3h), twiddle e^{i pi pos / h}
+      const int q1 = pos * (N >> (s + 1));
+      const double w1r = tw[2 * q1], w1i = sign * tw[2 * q1 + 1];
+      const double2 x0 = X[i0], x1 = cmul(X[i0 + h], w1r, w1i);
+      const double2 x2 = X[i0 + 2 * h], x3 = cmul(X[i0 + 3 * h], w1r, w1i);
+      double2 a0 = make_double2(x0.x + x1.x, x0.y + x1.y);
+      double2 a1 = make_double2(x0.x - x1.x, x0.y - x1.y);
+      double2 a2 = make_double2(x2.x + x3.x, x2.y + x3.y);
+      double2 a3 = make_double2(x2.x - x3.x, x2.y - x3.y);
+      // stage s+1: pairs (i0, i0+2h) with e^{i pi pos/(2h)}, (i0+h, i0+3h) with e^{i pi (pos+h)/(2h)}
+      const int q2 = pos * (N >> (s + 2));
+      const int q3 = (pos + h) * (N >> (s + 2));
+      a2 = cmul(a2, tw[2 * q2], sign * tw[2 * q2 + 1]);
+      a3 = cmul(a3, tw[2 * q3], sign * tw[2 * q3 + 1]);
+      X[i0] = make_double2(a0.x + a2.x, a0.y + a2.y);
+      X[i0 + 2 * h] = make_double2(a0.x - a2.x, a0.y - a2.y);
+      X[i0 + h] = make_double2(a1.x + a3.x, a1.y + a3.y);
+      X[i0 + 3 * h] = make_double2(a1.x - a3.x, a1.y - a3.y);
+    }
+  }
+  if (s < logN) {  // one radix-2 stage left
+    const int h = 1 << s;
     __syncthreads();
     for (int b = threadIdx.x; b < N / 2; b += kFftThreads) {
-      const int pos = b & (half - 1);
+      const int pos = b & (h - 1);
       const int i0 = ((b >> s) << (s + 1)) + pos;
-      const int i1 = i0 + half;
-      const int q = pos * stride;
-      const double wr = tw[2 * q], wi = sign * tw[2 * q + 1];
-      const double2 a = X[i0], c = X[i1];
-      const double br = c.x * wr - c.y * wi;
-      const double bi = c.x * wi + c.y * wr;
-      X[i0] = make_double2(a.x + br, a.y + bi);
-      X[i1] = make_double2(a.x - br, a.y - bi);
+      const int q = pos * (N >> (s + 1));
+      const double2 a = X[i0], c = cmul(X[i0 + h], tw[2 * q], sign * tw[2 * q + 1]);
+      X[i0] = make_double2(a.x + c.x, a.y + c.y);
+      X[i0 + h] = make_double2(a.x - c.x, a.y - c.y);
     }
   }
   __syncthreads();
 }
 
+// (ring, field) of this work-group: fields fastest within an XCD.
+__device__ __forceinline__ bool ring_field(int rings, int F, int& ring, int& f) {
+  const long long id = blockIdx.x;
+  const int xcd = static_cast<int>(id % kXcd);
+  const long long slot = id / kXcd;
+  const long long per = (static_cast<long long>(rings) * F + kXcd - 1) / kXcd;
+  const long long lin = xcd * per + slot;  // contiguous range of (ring, field) per XCD
+  if (slot >= per || lin >= static_cast<long long>(rings) * F) return false;
+  ring = static_cast<int>(lin / F);
+  f = static_cast<int>(lin % F);
+  return true;
+}
+
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, const double* __restrict__ tw,
-            int l, int R, int kind) {
+            int l, int R, int F, int kind) {
   extern __shared__ double2 X[];
-  const int ring = blockIdx.x;
-  const int f = blockIdx.y;
   const int L2 = 2 * l;
+  int ring, f;
+  if (!ring_field(L2, F, ring, f)) return;
   const int N = 4 * l;
-  int logN = 0;
-  while ((1 << logN) < N) ++logN;
+  const int logN = 31 - __clz(N);
   for (int b = threadIdx.x; b < N; b += kFftThreads) {
     double2 v = make_double2(0.0, 0.0);
     if (b < L2) {
       const long long row = static_cast<long long>(b) * L2 + ring;
       const double* src = Y + row * R + (kind == SHT_COMPLEX ? 4 * f : 2 * f);
-      v = make_double2(src[0], src[1]);
+      v = *reinterpret_cast<const double2*>(src);
     } else if (b > L2) {
       const int m = N - b;
       const long long row = static_cast<long long>(m) * L2 + ring;
       if (kind == SHT_COMPLEX) {
-        const double* src = Y + row * R + 4 * f + 2;
-        v = make_double2(src[0], src[1]);
+        v = *reinterpret_cast<const double2*>(Y + row * R + 4 * f + 2);
       } else {
-        const double* src = Y + row * R + 2 * f;
-        v = make_double2(src[0], -src[1]);  // g_{-m} = conj(g_m) for real fields
+        const double2 g = *reinterpret_cast<const double2*>(Y + row * R + 2 * f);
+        v = make_double2(g.x, -g.y);  // g_{-m} = conj(g_m) for real fields
       }
     }
     X[bitrev(b, logN)] = v;
@@ -81,14 +120,13 @@ k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, const doubl
 
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_analyze(const double* __restrict__ grid, double* __restrict__ Y, const double* __restrict__ tw,
-              int l, int R, int kind, double scale, double real_pos) {
+              int l, int R, int F, int kind, double scale, double real_pos) {
   extern __shared__ double2 X[];
-  const int ring = blockIdx.x;
-  const int f = blockIdx.y;
   const int L2 = 2 * l;
+  int ring, f;
+  if (!ring_field(L2, F, ring, f)) return;
   const int N = 4 * l;
-  int logN = 0;
-  while ((1 << logN) < N) ++logN;
+  const int logN = 31 - __clz(N);
   const long long rowbase = (static_cast<long long>(f) * L2 + ring) * N;
   for (int j = threadIdx.x; j < N; j += kFftThreads) {
     double2 v;
@@ -104,54 +142,47 @@ k_fft_analyze(const double* __restrict__ grid, double* __restrict__ Y, const dou
     if (kind == SHT_COMPLEX) {
       double* dst = Y + row * R + 4 * f;
       const double2 p = X[m];
-      dst[0] = p.x * scale;
-      dst[1] = p.y * scale;
-      if (m > 0) {
-        const double2 q = X[N - m];
-        dst[2] = q.x * scale;
-        dst[3] = q.y * scale;
-      } else {
-        dst[2] = 0.0;
-        dst[3] = 0.0;
-      }
+      const double2 q = m > 0 ? X[N - m] : make_double2(0.0, 0.0);
+      *reinterpret_cast<double2*>(dst) = make_double2(p.x * scale, p.y * scale);
+      *reinterpret_cast<double2*>(dst + 2) = make_double2(q.x * scale, q.y * scale);
     } else {
       // real fields store m >= 0 only; m > 0 stands for the pair +-m (factor real_pos)
-      double* dst = Y + row * R + 2 * f;
       const double2 p = X[m];
       const double sc = m > 0 ? scale * real_pos : scale;
-      dst[0] = p.x * sc;
-      dst[1] = p.y * sc;
+      *reinterpret_cast<double2*>(Y + row * R + 2 * f) = make_double2(p.x * sc, p.y * sc);
     }
   }
 }
 
-}  // namespace
-
-static hipError_t allow_lds(const void* fn, size_t bytes) {
+hipError_t allow_lds_fft(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(bytes));
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
+
+unsigned fft_grid(int l, int F) {
+  const long long per = (2LL * l * F + kXcd - 1) / kXcd;
+  return static_cast<unsigned>(per * kXcd);
+}
+
+}  // namespace
 
 hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
                             hipStream_t s) {
   const int N = 4 * P->l;
-  dim3 gridd(2 * P->l, F);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_synth), sizeof(double2) * N);
+  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), sizeof(double2) * N);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_synth, gridd, dim3(kFftThreads), sizeof(double2) * N, s, y, grid,
-                     P->d.twiddle, P->l, R, P->kind);
+  hipLaunchKernelGGL(k_fft_synth, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
+                     y, grid, P->d.twiddle, P->l, R, F, P->kind);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
                               double scale, double real_pos, hipStream_t s) {
   const int N = 4 * P->l;
-  dim3 gridd(2 * P->l, F);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_analyze), sizeof(double2) * N);
+  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), sizeof(double2) * N);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_analyze, gridd, dim3(kFftThreads), sizeof(double2) * N, s, grid, y,
-                     P->d.twiddle, P->l, R, P->kind, scale, real_pos);
+  hipLaunchKernelGGL(k_fft_analyze, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
+                     grid, y, P->d.twiddle, P->l, R, F, P->kind, scale, real_pos);
   return hipGetLastError();
 }
 

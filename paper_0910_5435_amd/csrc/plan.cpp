@@ -262,19 +262,34 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   std::vector<uint16_t> idx;
   std::vector<LevelTask> tasks;
   std::vector<FinalTask> finals;
+  std::vector<FactorBlock> fblocks;
   P->step_off.assign(Lmax + 1, 0);
   P->step_cnt.assign(Lmax + 1, 0);
   P->step_maxK.assign(Lmax + 1, 0);
   P->step_maxk.assign(Lmax + 1, 0);
+  P->step_fac.assign(Lmax + 1, 0.0);
+  P->step_rows_in.assign(Lmax + 1, 0.0);
+  P->step_rows_out.assign(Lmax + 1, 0.0);
   auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off) {
     idx_off = static_cast<int32_t>(idx.size());
     for (int v : B.skel) idx.push_back(static_cast<uint16_t>(v));
     for (int v : B.red) idx.push_back(static_cast<uint16_t>(v));
     fac_off = static_cast<int64_t>(fac.size());
     fac.insert(fac.end(), B.T.begin(), B.T.end());
+    if (!B.T.empty()) fblocks.push_back({fac_off, B.k, B.K - B.k});
   };
+  // Tasks of a step are independent; they are grouped into size classes (by input length
+  // K) so that each class launches with an LDS allocation fitting its own blocks, largest
+  // class first.  Factors are packed in launch order so the apply kernels stream them.
+  auto kclass = [](int K) { return K <= 96 ? 2 : (K <= 192 ? 1 : 0); };
+  struct Proto {
+    LevelTask tk;
+    const BfBlock* b[2];
+  };
+  P->step_classes.assign(Lmax + 1, {});
   for (int t = 0; t <= Lmax; ++t) {
     P->step_off[t] = static_cast<long long>(tasks.size());
+    std::vector<Proto> protos;
     for (int mp = 0; mp < npairs; ++mp) {
       const BfTree& T = trees[mp];
       if (T.L() < t) continue;
@@ -283,19 +298,15 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
         for (int c = 0; c < T.ncol(0); ++c) {
           const BfBlock& B = T.block(0, 0, c);
           if (B.K == 0) continue;
-          LevelTask tk{};
-          tk.in_row = P->in_base[mp] + c * T.C();
-          tk.K = B.K;
-          tk.out_row[0] = vb + voff[mp][0][c];
-          tk.out_row[1] = 0;
-          tk.k[0] = B.k;
-          tk.k[1] = -1;
-          push_block(B, tk.idx[0], tk.fac[0]);
-          tk.idx[1] = 0;
-          tk.fac[1] = 0;
-          tasks.push_back(tk);
-          P->step_maxK[t] = std::max(P->step_maxK[t], B.K);
-          P->step_maxk[t] = std::max(P->step_maxk[t], B.k);
+          Proto pr{};
+          pr.tk.in_row = P->in_base[mp] + c * T.C();
+          pr.tk.K = B.K;
+          pr.tk.out_row[0] = vb + voff[mp][0][c];
+          pr.tk.k[0] = B.k;
+          pr.tk.k[1] = -1;
+          pr.b[0] = &B;
+          pr.b[1] = nullptr;
+          protos.push_back(pr);
         }
       } else {
         const int ncp = T.ncol(t - 1), nc = T.ncol(t);
@@ -304,21 +315,47 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
             const BfBlock& Bt = T.block(t, 2 * q, cc);
             const BfBlock& Bb = T.block(t, 2 * q + 1, cc);
             if (Bt.K == 0) continue;
-            LevelTask tk{};
-            tk.in_row = vb + voff[mp][t - 1][q * ncp + 2 * cc];
-            tk.K = Bt.K;
-            tk.out_row[0] = vb + voff[mp][t][(2 * q) * nc + cc];
-            tk.out_row[1] = vb + voff[mp][t][(2 * q + 1) * nc + cc];
-            tk.k[0] = Bt.k;
-            tk.k[1] = Bb.k;
-            push_block(Bt, tk.idx[0], tk.fac[0]);
-            push_block(Bb, tk.idx[1], tk.fac[1]);
-            tasks.push_back(tk);
-            P->step_maxK[t] = std::max(P->step_maxK[t], Bt.K);
-            P->step_maxk[t] = std::max(P->step_maxk[t], std::max(Bt.k, Bb.k));
+            Proto pr{};
+            pr.tk.in_row = vb + voff[mp][t - 1][q * ncp + 2 * cc];
+            pr.tk.K = Bt.K;
+            pr.tk.out_row[0] = vb + voff[mp][t][(2 * q) * nc + cc];
+            pr.tk.out_row[1] = vb + voff[mp][t][(2 * q + 1) * nc + cc];
+            pr.tk.k[0] = Bt.k;
+            pr.tk.k[1] = Bb.k;
+            pr.b[0] = &Bt;
+            pr.b[1] = &Bb;
+            protos.push_back(pr);
           }
         }
       }
+    }
+    std::stable_sort(protos.begin(), protos.end(), [&](const Proto& a, const Proto& b) {
+      return kclass(a.tk.K) < kclass(b.tk.K);
+    });
+    for (size_t i = 0; i < protos.size(); ++i) {
+      Proto& pr = protos[i];
+      LevelTask tk = pr.tk;
+      push_block(*pr.b[0], tk.idx[0], tk.fac[0]);
+      int kmx = pr.b[0]->k;
+      double nf = static_cast<double>(pr.b[0]->T.size());
+      if (pr.b[1]) {
+        push_block(*pr.b[1], tk.idx[1], tk.fac[1]);
+        kmx = std::max(kmx, pr.b[1]->k);
+        nf += static_cast<double>(pr.b[1]->T.size());
+      }
+      const int cl = kclass(tk.K);
+      auto& cls = P->step_classes[t];
+      if (cls.empty() || cls.back().cls != cl)
+        cls.push_back({static_cast<long long>(tasks.size()) - P->step_off[t], 0, 0, 0, cl});
+      cls.back().cnt += 1;
+      cls.back().maxK = std::max(cls.back().maxK, tk.K);
+      cls.back().maxk = std::max(cls.back().maxk, kmx);
+      tasks.push_back(tk);
+      P->step_maxK[t] = std::max(P->step_maxK[t], tk.K);
+      P->step_maxk[t] = std::max(P->step_maxk[t], kmx);
+      P->step_fac[t] += nf;
+      P->step_rows_in[t] += tk.K;
+      P->step_rows_out[t] += tk.k[0] + (tk.k[1] > 0 ? tk.k[1] : 0);
     }
     P->step_cnt[t] = static_cast<long long>(tasks.size()) - P->step_off[t];
   }
@@ -339,9 +376,13 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
         ft.in_row[p] = P->v_base[2 * m + p] + voff[2 * m + p][L][r];
         ft.fac[p] = static_cast<int64_t>(fac.size());
         fac.insert(fac.end(), f.S.begin(), f.S.end());
+        if (!f.S.empty()) fblocks.push_back({ft.fac[p], f.h, f.k});
       }
       if (ft.h > 0) {
         finals.push_back(ft);
+        P->final_fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
+        P->final_rows_v += ft.k[0] + ft.k[1];
+        P->final_rows_y += 2.0 * ft.h;
         P->final_maxh = std::max(P->final_maxh, ft.h);
         P->final_maxk = std::max(P->final_maxk, std::max(ft.k[0], ft.k[1]));
       }
@@ -389,16 +430,24 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.invD), invD.data(), invD.size() * sizeof(double));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.D), D.data(), D.size() * sizeof(double));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.twiddle), tw.data(), tw.size() * sizeof(double));
+  // transposed copies for the analysis direction, built on the device
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.fac_t), nullptr, fac.size() * sizeof(double));
+  FactorBlock* dblocks = nullptr;
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&dblocks), fblocks.data(), fblocks.size() * sizeof(FactorBlock));
+  if (e == hipSuccess)
+    e = transpose_factors(P->d.fac, P->d.fac_t, dblocks, static_cast<long long>(fblocks.size()), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (dblocks) (void)hipFree(dblocks);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   P->stats.device_bytes =
-      static_cast<long long>(fac.size() * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
+      static_cast<long long>(2 * fac.size() * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
                              finals.size() * sizeof(FinalTask) + pd.size() * sizeof(PairDesc) +
                              (invD.size() + D.size() + tw.size()) * 8);
   return SHT_OK;
 }
 
 void free_plan_device(sht_plan_s* P) {
-  void* ptrs[] = {P->d.fac,   P->d.fac_hi, P->d.fac_lo, P->d.idx,    P->d.tasks,
+  void* ptrs[] = {P->d.fac,    P->d.fac_t, P->d.fac_hi, P->d.fac_lo, P->d.idx,    P->d.tasks,
                   P->d.finals, P->d.pairs, P->d.invD,   P->d.D,      P->d.twiddle};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -44,8 +44,15 @@ struct PairDesc {
   int32_t in_base;    // first XIN row
 };
 
+// One stored factor matrix (T of an ID or S of a final skeleton), column-major.
+struct FactorBlock {
+  int64_t off;
+  int32_t rows, cols;
+};
+
 struct DeviceFactors {
-  double* fac = nullptr;       // T and S entries (FP64)
+  double* fac = nullptr;       // T and S entries (FP64), column-major, read by synthesis
+  double* fac_t = nullptr;     // the same matrices transposed (same offsets), read by analysis
   float* fac_hi = nullptr;     // FP32 split copies (allocated on first split/fp32 use)
   float* fac_lo = nullptr;
   uint16_t* idx = nullptr;     // skel/red index lists
@@ -55,6 +62,35 @@ struct DeviceFactors {
   double* invD = nullptr;      // 1 / sqrt(2 w_i) on the positive nodes
   double* D = nullptr;         // sqrt(2 w_i)
   double* twiddle = nullptr;   // e^{2 pi i j / N}, j = 0..N-1 (interleaved)
+};
+
+// Optional per-stage timing: HIP events recorded around every kernel launch of a
+// transform on the caller's stream, accumulated by stage name when read.
+struct ProfRecord {
+  std::string name;
+  double ms = 0.0;
+  long long launches = 0;
+  double flops = 0.0;  // algorithmic flops per launch
+  double bytes = 0.0;  // algorithmic HBM bytes per launch
+};
+struct ProfPending {
+  int rec;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRecord> recs;
+  std::vector<ProfPending> pending;
+  int find_or_add(const std::string& name, double flops, double bytes);
+  int flush();  // waits for the recorded events and accumulates their times
+  void clear();
+};
+
+// A contiguous run of tasks of one step launched together (one LDS size).
+struct LaunchClass {
+  long long off, cnt;  // task range relative to the step's first task
+  int maxK, maxk;      // largest input length and output rank in the range
+  int cls;
 };
 
 }  // namespace sht
@@ -74,7 +110,12 @@ struct sht_plan_s {
   long long n_fac = 0, n_fac_split = 0, n_idx = 0;
   std::vector<long long> step_off, step_cnt;  // level tasks per step (t = 0..Lmax)
   std::vector<int> step_maxK, step_maxk;      // largest input / output length per step
+  std::vector<std::vector<sht::LaunchClass>> step_classes;
   int final_maxk = 0, final_maxh = 0;
+  // algorithmic work per step: factor entries, input rows, output rows (per R column)
+  std::vector<double> step_fac, step_rows_in, step_rows_out;
+  double final_fac = 0, final_rows_v = 0, final_rows_y = 0;
+  sht::Profiler prof;
   long long n_final = 0;
   long long n_pairs = 0;
   sht::DeviceFactors d;
@@ -98,6 +139,14 @@ hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, 
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
                               double scale, double real_pos, hipStream_t s);
 hipError_t split_factors(sht_plan_s* P, hipStream_t s);
+bool mfma_ok(int R);
+hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
+                             double* out, int R, hipStream_t s);
+hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
+                             double* v0w, double* v1w, double* y, const double* yin, int R,
+                             bool adjoint, hipStream_t s);
+hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock* blocks,
+                             long long nblocks, hipStream_t s);
 
 // Legendre column generator (legendre_cols.hip): recurrence state for a batch of pairs.
 struct ColumnBatch {

@@ -64,7 +64,10 @@ def test_column_kernel_matches_oracle(l, C, orders, tol):
     print(f"columns l={l}: max abs diff vs oracle {worst:.3e}")
 
 
-@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5)])
+# F % 4 == 0 selects the FP64 matrix-core kernels (R = 4F a multiple of 16), the rest the
+# vector kernels; the column tile is 64, 32 or 16 wide depending on R.
+@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5),
+                                   (64, 16, 4), (128, 32, 8), (256, 64, 16)])
 def test_synth_matches_oracle(l, C, F):
     P = _plan(l, C)
     beta = syn.coefficients(l, F, seed=0, power=1.0)
@@ -76,7 +79,8 @@ def test_synth_matches_oracle(l, C, F):
     assert err.max() < FP64_TOL
 
 
-@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5)])
+@pytest.mark.parametrize("l,C,F", [(32, 8, 1), (32, 8, 3), (256, 64, 1), (64, 16, 5),
+                                   (64, 16, 4), (128, 32, 8), (256, 64, 16)])
 def test_analyze_matches_oracle(l, C, F):
     P = _plan(l, C)
     g = syn.grid(l, F, seed=1)  # any grid: analysis is a linear map on all of them
@@ -87,7 +91,7 @@ def test_analyze_matches_oracle(l, C, F):
     assert err.max() < FP64_TOL
 
 
-@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 32, 1)])
+@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 32, 1), (64, 16, 4)])
 def test_adjoint_matches_oracle(l, C, F):
     P = _plan(l, C)
     r = syn.grid(l, F, seed=2)
@@ -122,7 +126,7 @@ def test_worked_example_l1_on_gpu():
         np.testing.assert_allclose(got, ref, atol=1e-15)
 
 
-@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 64, 1)])
+@pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 64, 1), (64, 16, 8)])
 def test_real_fields(l, C, F):
     P = _plan(l, C, kind="real")
     beta = syn.coefficients(l, F, seed=4, kind="real")

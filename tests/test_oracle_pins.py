@@ -304,6 +304,11 @@ def test_subset_routines_agree_with_full():
     f = oracle.synth(beta, l)
     rings = [0, 5, 2 * l - 1]
     np.testing.assert_allclose(oracle.ring_values(beta, l, rings), f[:, rings], atol=1e-14)
+    keep = [0, 2, 5]
+    masked = beta.copy()
+    ms = syn.orders_canonical(l)
+    masked[:, ~np.isin(np.abs(ms), keep)] = 0.0
+    np.testing.assert_allclose(oracle.synth(beta, l, orders=keep), oracle.synth(masked, l), atol=1e-14)
     full = oracle.analyze(f, l)
     part = oracle.analyze_orders(f, l, [0, 3, -7])
     for m in [0, 3, -3, 7, -7]:
