@@ -189,9 +189,15 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const std::string fs = fsuffix(F);
-  STAGE("synth.layout" + fs, layout_work(P, F, R), launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
-  STAGE("synth.level0" + fs, level_work(P, 0, R),
-        launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
+  if (mfma_ok(R)) {  // the leaf kernels gather straight from the coefficient layout
+    Work wk = level_work(P, 0, R);  // its input rows are the coefficients themselves
+    STAGE("synth.level0" + fs, wk,
+          launch_level(P, 0, false, nullptr, w.v0, R, precision, s, const_cast<double*>(coeff)));
+  } else {
+    STAGE("synth.layout" + fs, layout_work(P, F, R), launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
+    STAGE("synth.level0" + fs, level_work(P, 0, R),
+          launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
+  }
   for (int t = 1; t <= P->Lmax; ++t) {
     const double* in = (t - 1) % 2 ? w.v1 : w.v0;
     double* out = t % 2 ? w.v1 : w.v0;
@@ -226,9 +232,14 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
     STAGE(pre + "level" + std::to_string(t) + fs, level_work(P, t, R),
           launch_level(P, t, true, in, out, R, precision, s));
   }
-  STAGE(pre + "level0" + fs, level_work(P, 0, R),
-        launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
-  STAGE(pre + "layout" + fs, layout_work(P, F, R), launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
+  if (mfma_ok(R)) {  // the transposed leaf kernels scatter straight into the coefficient layout
+    STAGE(pre + "level0" + fs, level_work(P, 0, R),
+          launch_level(P, 0, true, w.v0, nullptr, R, precision, s, coeff));
+  } else {
+    STAGE(pre + "level0" + fs, level_work(P, 0, R),
+          launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
+    STAGE(pre + "layout" + fs, layout_work(P, F, R), launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
+  }
   return SHT_OK;
 }
 

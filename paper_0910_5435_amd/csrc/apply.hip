@@ -298,9 +298,9 @@ hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* c
 }
 
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in, double* out,
-                        int R, int precision, hipStream_t s) {
+                        int R, int precision, hipStream_t s, double* coeff) {
   (void)precision;
-  if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, s);
+  if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, s, coeff);
   const long long cnt = P->step_cnt[step];
   if (cnt == 0) return hipSuccess;
   const LevelTask* tasks = P->d.tasks + P->step_off[step];

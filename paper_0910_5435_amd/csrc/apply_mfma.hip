@@ -52,12 +52,46 @@ inline unsigned xcd_grid(long long ntasks, int nblk) {
 template <int NT>
 constexpr int ldp() { return NT + 2; }
 
+// Where a leaf task's vector rows live when they are read from / written to the caller's
+// coefficient array directly (the layout change fused into the leaf level).
+struct CoefIO {
+  double* coeff;  // null: use the internal row buffer instead
+  const PairDesc* pairs;
+  long long ncoef;
+  int l, kind;
+};
+
+// Visits the K x NT block of a leaf task (rows j of pair mp starting at column j0; local
+// columns c of the NT-column block c0) in an order where consecutive threads touch
+// consecutive degrees of one (field, sign): fn(j, c, position or -1 if no such entry).
+template <int NT, typename Fn>
+__device__ __forceinline__ void for_leaf_block(const CoefIO& io, int mp_m, int mp_p, int j0, int K,
+                                               long long c0, Fn&& fn) {
+  for (int e = threadIdx.x; e < K * NT; e += 256) {
+    const int cc = e & 1;
+    const int j = (e >> 1) % K;
+    const int g = (e >> 1) / K;  // (field, sign) group for complex, field for real
+    const int c = g * 2 + cc;
+    const int col = static_cast<int>(c0) + c;
+    const int k = mp_m + mp_p + 2 * (j0 + j);
+    long long pos;
+    if (io.kind == SHT_COMPLEX) {
+      const int f = col >> 2, s = (col >> 1) & 1;
+      pos = (mp_m == 0 && s == 1) ? -1 : coeff_pos(io.l, SHT_COMPLEX, io.ncoef, f, mp_m, s, k, cc);
+    } else {
+      const int f = col >> 1;
+      pos = (mp_m == 0 && cc == 1) ? -2 : coeff_pos(io.l, SHT_REAL, io.ncoef, f, mp_m, 0, k, cc);
+    }
+    fn(j, c, pos);
+  }
+}
+
 // ------------------------------------------------------------------- level, synthesis
 template <int NT>
 __global__ void __launch_bounds__(256)
 k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk,
                    const double* __restrict__ fac, const uint16_t* __restrict__ idx,
-                   const double* __restrict__ in, double* __restrict__ out, int R) {
+                   const double* __restrict__ in, double* __restrict__ out, int R, CoefIO io) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   extern __shared__ double lds[];
@@ -71,7 +105,12 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * LD);      // [skel0 red0 skel1 red1]
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
   const int nidx = (k0 > 0 ? K : 0) + (k1 > 0 ? K : 0);
-  {
+  if (io.coeff && tk.mp >= 0) {
+    const PairDesc pd = io.pairs[tk.mp];
+    const double* cf = io.coeff;
+    for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0,
+                       [&](int j, int c, long long pos) { xs[j * LD + c] = pos >= 0 ? cf[pos] : 0.0; });
+  } else {
     const double* src = in + static_cast<long long>(tk.in_row) * R + c0;
     for (int e = threadIdx.x; e < K * (NT / 2); e += 256) {
       const int row = e / (NT / 2), c2 = e % (NT / 2);
@@ -79,6 +118,8 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
       xs[row * LD + 2 * c2] = v.x;
       xs[row * LD + 2 * c2 + 1] = v.y;
     }
+  }
+  {
     if (k0 > 0)
       for (int e = threadIdx.x; e < K; e += 256) ix[e] = idx[tk.idx[0] + e];
     if (k1 > 0)
@@ -113,18 +154,40 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
       }
     }
     const int i0 = mt0 * 16 + lc, i1 = i0 + 16;
-    for (int kk0 = 0; kk0 < nr; kk0 += 4) {
-      const int kk = kk0 + lr;
-      const bool kin = kk < nr;
-      const double* Tc = T + static_cast<long long>(kk) * k;
-      const double a0 = (kin && i0 < k) ? Tc[i0] : 0.0;
-      const double a1 = (kin && two && i1 < k) ? Tc[i1] : 0.0;
-      const double* xr = xs + (kin ? red[kk] : 0) * LD + lc;
+    // factor fragments are fetched PF K-steps ahead (double-buffered in registers) so the
+    // global-load latency overlaps the MFMAs of the previous steps
+    constexpr int PF = 4;
+    const int nsteps = (nr + 3) >> 2;
+    double a0c[PF], a1c[PF], a0n[PF], a1n[PF];
+    auto fetch = [&](int s0, double* d0, double* d1) {
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) {
-        const double b = kin ? xr[n * 16] : 0.0;
-        acc[0][n] = mfma(a0, b, acc[0][n]);
-        if (two) acc[1][n] = mfma(a1, b, acc[1][n]);
+      for (int u = 0; u < PF; ++u) {
+        const int kk = (s0 + u) * 4 + lr;
+        const bool kin = kk < nr;
+        const double* Tc = T + static_cast<long long>(kk) * k;
+        d0[u] = (kin && i0 < k) ? Tc[i0] : 0.0;
+        d1[u] = (kin && two && i1 < k) ? Tc[i1] : 0.0;
+      }
+    };
+    fetch(0, a0c, a1c);
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+      if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n);
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int kk = (s0 + u) * 4 + lr;
+        const bool kin = kk < nr;
+        const double* xr = xs + (kin ? red[kk] : 0) * LD + lc;
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) {
+          const double b = kin ? xr[n * 16] : 0.0;
+          acc[0][n] = mfma(a0c[u], b, acc[0][n]);
+          if (two) acc[1][n] = mfma(a1c[u], b, acc[1][n]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        a0c[u] = a0n[u];
+        a1c[u] = a1n[u];
       }
     }
     double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
@@ -150,7 +213,7 @@ template <int NT>
 __global__ void __launch_bounds__(256)
 k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk,
                    const double* __restrict__ fac_t, const uint16_t* __restrict__ idx,
-                   const double* __restrict__ win, double* __restrict__ xout, int R) {
+                   const double* __restrict__ win, double* __restrict__ xout, int R, CoefIO io) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   extern __shared__ double lds[];
@@ -199,18 +262,38 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 #pragma unroll
         for (int n = 0; n < NTL; ++n) acc[u][n] = zero4();
       const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
-      for (int ii0 = 0; ii0 < k; ii0 += 4) {
-        const int i = ii0 + lr;
-        const bool iin = i < k;
-        const double* Tr = Tt + static_cast<long long>(i) * nr;
-        const double a0 = (iin && j0 < nr) ? Tr[j0] : 0.0;
-        const double a1 = (iin && two && j1 < nr) ? Tr[j1] : 0.0;
-        const double* wr = w + (iin ? i : 0) * LD + lc;
+      constexpr int PF = 4;
+      const int nsteps = (k + 3) >> 2;
+      double a0c[PF], a1c[PF], a0n[PF], a1n[PF];
+      auto fetch = [&](int s0, double* d0, double* d1) {
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) {
-          const double b = iin ? wr[n * 16] : 0.0;
-          acc[0][n] = mfma(a0, b, acc[0][n]);
-          if (two) acc[1][n] = mfma(a1, b, acc[1][n]);
+        for (int u = 0; u < PF; ++u) {
+          const int i = (s0 + u) * 4 + lr;
+          const bool iin = i < k;
+          const double* Tr = Tt + static_cast<long long>(i) * nr;
+          d0[u] = (iin && j0 < nr) ? Tr[j0] : 0.0;
+          d1[u] = (iin && two && j1 < nr) ? Tr[j1] : 0.0;
+        }
+      };
+      fetch(0, a0c, a1c);
+      for (int s0 = 0; s0 < nsteps; s0 += PF) {
+        if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int i = (s0 + u) * 4 + lr;
+          const bool iin = i < k;
+          const double* wr = w + (iin ? i : 0) * LD + lc;
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) {
+            const double b = iin ? wr[n * 16] : 0.0;
+            acc[0][n] = mfma(a0c[u], b, acc[0][n]);
+            if (two) acc[1][n] = mfma(a1c[u], b, acc[1][n]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          a0c[u] = a0n[u];
+          a1c[u] = a1n[u];
         }
       }
 #pragma unroll
@@ -240,6 +323,18 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
         *dst += w[i * LD + c];
     }
     __syncthreads();
+  }
+  if (io.coeff && tk.mp >= 0) {
+    const PairDesc pd = io.pairs[tk.mp];
+    double* cf = io.coeff;
+    for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0, [&](int j, int c, long long pos) {
+      if (pos >= 0)
+        cf[pos] = acc_l[j * LD + c];
+      else if (pos == -2)  // imaginary part at m = 0 of a real field
+        cf[coeff_pos(io.l, SHT_REAL, io.ncoef, static_cast<int>((c0 + c) >> 1), 0, 0,
+                     pd.p + 2 * (tk.in_row - pd.in_base + j), 1)] = 0.0;
+    });
+    return;
   }
   double* xb = xout + static_cast<long long>(tk.in_row) * R + c0;
   for (int e = threadIdx.x; e < K * (NT / 2); e += 256) {
@@ -296,21 +391,41 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
     }
     const int i = mt * 16 + lc;
     const bool iin = i < h;
-    for (int a0 = 0; a0 < k0; a0 += 4) {
-      const int a = a0 + lr;
-      const bool ain = a < k0;
-      const double av = (ain && iin) ? S0[static_cast<long long>(a) * h + i] : 0.0;
-      const double* wr = w0 + (ain ? a : 0) * LD + lc;
+    // both parities in one prefetched loop: step s < n0 feeds E, the rest feed O
+    constexpr int PF = 4;
+    const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 + n1;
+    double ac[PF], an[PF];
+    auto fetch = [&](int s0, double* d) {
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) E[n] = mfma(av, ain ? wr[n * 16] : 0.0, E[n]);
-    }
-    for (int a0 = 0; a0 < k1; a0 += 4) {
-      const int a = a0 + lr;
-      const bool ain = a < k1;
-      const double av = (ain && iin) ? S1[static_cast<long long>(a) * h + i] : 0.0;
-      const double* wr = w1 + (ain ? a : 0) * LD + lc;
+      for (int u = 0; u < PF; ++u) {
+        const int st = s0 + u;
+        const bool odd = st >= n0;
+        const int a = (odd ? st - n0 : st) * 4 + lr;
+        const bool ain = st < nsteps && a < (odd ? k1 : k0);
+        d[u] = (ain && iin) ? (odd ? S1 : S0)[static_cast<long long>(a) * h + i] : 0.0;
+      }
+    };
+    fetch(0, ac);
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+      if (s0 + PF < nsteps) fetch(s0 + PF, an);
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) O[n] = mfma(av, ain ? wr[n * 16] : 0.0, O[n]);
+      for (int u = 0; u < PF; ++u) {
+        const int st = s0 + u;
+        if (st >= nsteps) break;
+        const bool odd = st >= n0;
+        const int a = (odd ? st - n0 : st) * 4 + lr;
+        const bool ain = a < (odd ? k1 : k0);
+        const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc;
+        if (!odd) {
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) E[n] = mfma(ac[u], ain ? wr[n * 16] : 0.0, E[n]);
+        } else {
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) O[n] = mfma(ac[u], ain ? wr[n * 16] : 0.0, O[n]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) ac[u] = an[u];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -381,13 +496,29 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
       const int a = (p ? q - nm0 : q) * 16 + lc;
       const double* St = fac_t + ft.fac[p];  // k x h column-major
       const double* src = eo[p];
-      for (int ii0 = 0; ii0 < ih; ii0 += 4) {
-        const int i = ii0 + lr;
-        const bool iin = i < ih;
-        const double av = (iin && a < k) ? St[static_cast<long long>(i0 + i) * k + a] : 0.0;
-        const double* er = src + (iin ? i : 0) * LD + lc;
+      constexpr int PF = 4;
+      const int nsteps = (ih + 3) >> 2;
+      double ac[PF], an[PF];
+      auto fetch = [&](int s0, double* d) {
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) acc[u][n] = mfma(av, iin ? er[n * 16] : 0.0, acc[u][n]);
+        for (int w = 0; w < PF; ++w) {
+          const int i = (s0 + w) * 4 + lr;
+          d[w] = (i < ih && a < k) ? St[static_cast<long long>(i0 + i) * k + a] : 0.0;
+        }
+      };
+      fetch(0, ac);
+      for (int s0 = 0; s0 < nsteps; s0 += PF) {
+        if (s0 + PF < nsteps) fetch(s0 + PF, an);
+#pragma unroll
+        for (int w = 0; w < PF; ++w) {
+          const int i = (s0 + w) * 4 + lr;
+          const bool iin = i < ih;
+          const double* er = src + (iin ? i : 0) * LD + lc;
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) acc[u][n] = mfma(ac[w], iin ? er[n * 16] : 0.0, acc[u][n]);
+        }
+#pragma unroll
+        for (int w = 0; w < PF; ++w) ac[w] = an[w];
       }
     }
   }
@@ -443,12 +574,14 @@ bool mfma_ok(int R) { return R % 16 == 0; }
 
 static hipError_t launch_level_class(const sht_plan_s* P, int step, const LaunchClass& lc,
                                      bool transpose, const double* in, double* out, int R,
-                                     hipStream_t s);
+                                     const CoefIO& io, hipStream_t s);
 
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, hipStream_t s) {
+                             double* out, int R, hipStream_t s, double* coeff) {
+  CoefIO io{coeff, P->d.pairs,
+            P->kind == SHT_COMPLEX ? 4LL * P->l * P->l : 2LL * P->l * P->l + P->l, P->l, P->kind};
   for (const LaunchClass& lc : P->step_classes[step]) {
-    hipError_t e = launch_level_class(P, step, lc, transpose, in, out, R, s);
+    hipError_t e = launch_level_class(P, step, lc, transpose, in, out, R, io, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -456,7 +589,7 @@ hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, cons
 
 static hipError_t launch_level_class(const sht_plan_s* P, int step, const LaunchClass& lc,
                                      bool transpose, const double* in, double* out, int R,
-                                     hipStream_t s) {
+                                     const CoefIO& io, hipStream_t s) {
   const long long cnt = lc.cnt;
   if (cnt == 0) return hipSuccess;
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
@@ -474,19 +607,19 @@ static hipError_t launch_level_class(const sht_plan_s* P, int step, const Launch
     const size_t lds = static_cast<size_t>(K) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
     if (NT == 32) {
       if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_synth_mfma<32>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_synth_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R);
+      hipLaunchKernelGGL(k_level_synth_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R, io);
     } else {
       if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_synth_mfma<16>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R);
+      hipLaunchKernelGGL(k_level_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R, io);
     }
   } else {
     const size_t lds = static_cast<size_t>(K + 2 * k) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
     if (NT == 32) {
       if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_trans_mfma<32>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_trans_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R);
+      hipLaunchKernelGGL(k_level_trans_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R, io);
     } else {
       if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_trans_mfma<16>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_trans_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R);
+      hipLaunchKernelGGL(k_level_trans_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R, io);
     }
   }
   return hipGetLastError();
@@ -495,23 +628,29 @@ static hipError_t launch_level_class(const sht_plan_s* P, int step, const Launch
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
                              bool adjoint, hipStream_t s) {
-  const long long cnt = P->n_final;
-  if (cnt == 0) return hipSuccess;
+  const long long total = P->n_final;
+  if (total == 0) return hipSuccess;
   hipError_t e;
   if (!transpose) {
-    const long long rows = 2LL * P->final_maxk;
-    const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
-    const int nblk = R / NT;
-    const dim3 grid(xcd_grid(cnt, nblk));
-    const size_t lds = static_cast<size_t>(2 * P->final_maxk) * (NT + 2) * 8 + 16;
-    if (NT == 32) {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<32>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_final_synth_mfma<32>, grid, dim3(256), lds, s, P->d.finals, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
-    } else {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<16>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_final_synth_mfma<16>, grid, dim3(256), lds, s, P->d.finals, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
+    for (const LaunchClass& lc : P->final_classes) {
+      const long long cnt = lc.cnt;
+      const FinalTask* tasks = P->d.finals + lc.off;
+      const long long rows = 2LL * lc.maxk;
+      const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
+      const int nblk = R / NT;
+      const dim3 grid(xcd_grid(cnt, nblk));
+      const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 16;
+      if (NT == 32) {
+        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<32>), lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_final_synth_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
+      } else {
+        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<16>), lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_final_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   } else {
+    const long long cnt = total;
     if (P->final_maxk > 6 * 16 * 4 / 2) return hipErrorInvalidValue;  // k0 + k1 <= 384
     const double* scale = adjoint ? P->d.invD : P->d.D;
     const double half = adjoint ? 1.0 : 0.5;

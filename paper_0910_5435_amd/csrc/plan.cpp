@@ -304,6 +304,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
           pr.tk.out_row[0] = vb + voff[mp][0][c];
           pr.tk.k[0] = B.k;
           pr.tk.k[1] = -1;
+          pr.tk.mp = mp;
           pr.b[0] = &B;
           pr.b[1] = nullptr;
           protos.push_back(pr);
@@ -322,6 +323,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
             pr.tk.out_row[1] = vb + voff[mp][t][(2 * q + 1) * nc + cc];
             pr.tk.k[0] = Bt.k;
             pr.tk.k[1] = Bb.k;
+            pr.tk.mp = -1;
             pr.b[0] = &Bt;
             pr.b[1] = &Bb;
             protos.push_back(pr);
@@ -359,34 +361,58 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     }
     P->step_cnt[t] = static_cast<long long>(tasks.size()) - P->step_off[t];
   }
+  // Final skeleton tasks, grouped like the level tasks by rank (LDS size per launch).
+  auto fclass = [](int k) { return k <= 96 ? 1 : 0; };
+  struct FProto {
+    FinalTask ft;
+    const BfFinal* f[2];
+  };
+  std::vector<FProto> fprotos;
   for (int m = 0; m < L2; ++m) {
     const BfTree& T0 = trees[2 * m];
     const BfTree& T1 = trees[2 * m + 1];
     const int L = T0.L();
     for (int r = 0; r < (1 << L); ++r) {
-      FinalTask ft{};
+      FProto pr{};
+      FinalTask& ft = pr.ft;
       ft.m = m;
       ft.row0 = T0.row_lo(L, r);
       ft.h = T0.row_h(L, r);
       ft.vbuf = L % 2;
       for (int p = 0; p < 2; ++p) {
         const BfTree& T = p ? T1 : T0;
-        const BfFinal& f = T.final_block(r);
-        ft.k[p] = f.k;
+        pr.f[p] = &T.final_block(r);
+        ft.k[p] = pr.f[p]->k;
         ft.in_row[p] = P->v_base[2 * m + p] + voff[2 * m + p][L][r];
-        ft.fac[p] = static_cast<int64_t>(fac.size());
-        fac.insert(fac.end(), f.S.begin(), f.S.end());
-        if (!f.S.empty()) fblocks.push_back({ft.fac[p], f.h, f.k});
       }
-      if (ft.h > 0) {
-        finals.push_back(ft);
-        P->final_fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
-        P->final_rows_v += ft.k[0] + ft.k[1];
-        P->final_rows_y += 2.0 * ft.h;
-        P->final_maxh = std::max(P->final_maxh, ft.h);
-        P->final_maxk = std::max(P->final_maxk, std::max(ft.k[0], ft.k[1]));
-      }
+      if (ft.h > 0) fprotos.push_back(pr);
     }
+  }
+  std::stable_sort(fprotos.begin(), fprotos.end(), [&](const FProto& a, const FProto& b) {
+    return fclass(std::max(a.ft.k[0], a.ft.k[1])) < fclass(std::max(b.ft.k[0], b.ft.k[1]));
+  });
+  P->final_classes.clear();
+  for (FProto& pr : fprotos) {
+    FinalTask ft = pr.ft;
+    for (int p = 0; p < 2; ++p) {
+      const BfFinal& f = *pr.f[p];
+      ft.fac[p] = static_cast<int64_t>(fac.size());
+      fac.insert(fac.end(), f.S.begin(), f.S.end());
+      if (!f.S.empty()) fblocks.push_back({ft.fac[p], f.h, f.k});
+    }
+    const int kmx = std::max(ft.k[0], ft.k[1]);
+    const int cl = fclass(kmx);
+    if (P->final_classes.empty() || P->final_classes.back().cls != cl)
+      P->final_classes.push_back({static_cast<long long>(finals.size()), 0, 0, 0, cl});
+    P->final_classes.back().cnt += 1;
+    P->final_classes.back().maxK = std::max(P->final_classes.back().maxK, ft.h);
+    P->final_classes.back().maxk = std::max(P->final_classes.back().maxk, kmx);
+    finals.push_back(ft);
+    P->final_fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
+    P->final_rows_v += ft.k[0] + ft.k[1];
+    P->final_rows_y += 2.0 * ft.h;
+    P->final_maxh = std::max(P->final_maxh, ft.h);
+    P->final_maxk = std::max(P->final_maxk, kmx);
   }
   P->n_final = static_cast<long long>(finals.size());
   P->n_fac = static_cast<long long>(fac.size());

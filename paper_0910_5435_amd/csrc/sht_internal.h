@@ -22,8 +22,25 @@ struct LevelTask {
   int32_t out_row[2]; // first row of each output block
   int32_t k[2];       // rank of each output block; k[1] = -1 for a leaf
   int32_t idx[2];     // offset of [skel (k) | red (K-k)] in the index pool
+  int32_t mp;         // leaf tasks: pair index 2m + p (their input comes from coefficients)
   int64_t fac[2];     // offset of T (k x (K-k), column-major) in the factor pool
 };
+
+// Position of Re/Im part `c` of beta_k^{+-m} (s = 0: +m, s = 1: -m) of field f in the
+// canonical coefficient layout (orders ascending, +m block then -m block, degrees
+// contiguous; real fields store m >= 0 only).
+__host__ __device__ inline long long coeff_pos(int l, int kind, long long ncoef, int f, int m, int s,
+                                               int k, int c) {
+  const long long L2 = 2LL * l;
+  long long base;
+  if (kind == SHT_REAL) {
+    base = static_cast<long long>(m) * L2 - static_cast<long long>(m) * (m - 1) / 2;
+  } else {
+    base = m == 0 ? 0 : L2 + 2LL * (m - 1) * L2 - static_cast<long long>(m - 1) * m;
+    if (s) base += L2 - m;
+  }
+  return (static_cast<long long>(f) * ncoef + base + (k - m)) * 2 + c;
+}
 
 // Final skeleton product for one order m and one row node r at level L, both
 // parities at once, followed by the parity unfold g(+-x) = E +- O and the row
@@ -111,6 +128,7 @@ struct sht_plan_s {
   std::vector<long long> step_off, step_cnt;  // level tasks per step (t = 0..Lmax)
   std::vector<int> step_maxK, step_maxk;      // largest input / output length per step
   std::vector<std::vector<sht::LaunchClass>> step_classes;
+  std::vector<sht::LaunchClass> final_classes;  // maxK holds the largest row count h
   int final_maxk = 0, final_maxh = 0;
   // algorithmic work per step: factor entries, input rows, output rows (per R column)
   std::vector<double> step_fac, step_rows_in, step_rows_out;
@@ -130,7 +148,7 @@ hipError_t launch_coeff_to_xin(const sht_plan_s* P, const double* coeff, double*
 hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* coeff, int F,
                                int R, hipStream_t s);
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in,
-                        double* out, int R, int precision, hipStream_t s);
+                        double* out, int R, int precision, hipStream_t s, double* coeff = nullptr);
 hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R,
                         int precision, bool adjoint, hipStream_t s);
@@ -140,8 +158,10 @@ hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y
                               double scale, double real_pos, hipStream_t s);
 hipError_t split_factors(sht_plan_s* P, hipStream_t s);
 bool mfma_ok(int R);
+// coeff (leaf step only, may be null): read the leaf input from (synthesis) or write the
+// leaf output to (transposed) the caller's coefficient array instead of the row buffer.
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, hipStream_t s);
+                             double* out, int R, hipStream_t s, double* coeff);
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
                              bool adjoint, hipStream_t s);
