@@ -206,9 +206,11 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 }
 
 // ------------------------------------------------------------------ level, transposed
-// LDS: w_0 (k0 x NT), w_1 (k1 x NT), the accumulated input block (K x NT), index lists.
-// Output block o contributes T_o^T w_o at rows red_o and w_o at rows skel_o (assigned for
-// o = 0, added for o = 1; every row gets exactly one term per block).
+// LDS holds the accumulated input block (K x NT) and the index lists; the vectors w_o of
+// the output blocks are read as B fragments straight from global memory (prefetched with
+// the factor fragments).  Output block o contributes T_o^T w_o at rows red_o and w_o at
+// rows skel_o (assigned for o = 0, added for o = 1; every row gets exactly one term per
+// block).
 template <int NT>
 __global__ void __launch_bounds__(256)
 k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk,
@@ -225,32 +227,20 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   const long long c0 = static_cast<long long>(blk) * NT;
   const int nouts = tk.k[1] < 0 ? 1 : 2;
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
-  double* w0 = lds;
-  double* w1 = w0 + k0 * LD;
-  double* acc_l = w1 + k1 * LD;
+  double* acc_l = lds;
   uint16_t* ix = reinterpret_cast<uint16_t*>(acc_l + K * LD);  // [skel0 red0 skel1 red1]
-  for (int o = 0; o < nouts; ++o) {
-    const int k = o ? k1 : k0;
-    double* w = o ? w1 : w0;
-    const double* src = win + static_cast<long long>(tk.out_row[o]) * R + c0;
-    for (int e = threadIdx.x; e < k * (NT / 2); e += 256) {
-      const int row = e / (NT / 2), c2 = e % (NT / 2);
-      const double2 v = *reinterpret_cast<const double2*>(src + static_cast<long long>(row) * R + 2 * c2);
-      w[row * LD + 2 * c2] = v.x;
-      w[row * LD + 2 * c2 + 1] = v.y;
-    }
+  for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
-  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
   for (int o = 0; o < nouts; ++o) {
     const int k = o ? k1 : k0;
     const int nr = K - k;
-    const double* w = o ? w1 : w0;
     const uint16_t* skel = ix + o * K;
     const uint16_t* red = skel + k;
     const double* Tt = fac_t + tk.fac[o];  // nr x k column-major
+    const double* wb = win + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
     const int nm = (nr + 15) >> 4;
     const int np = (nm + 1) >> 1;
     for (int q = wave; q < np; q += 4) {
@@ -264,8 +254,8 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
       const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
       constexpr int PF = 4;
       const int nsteps = (k + 3) >> 2;
-      double a0c[PF], a1c[PF], a0n[PF], a1n[PF];
-      auto fetch = [&](int s0, double* d0, double* d1) {
+      double a0c[PF], a1c[PF], a0n[PF], a1n[PF], bc[PF][NTL], bn[PF][NTL];
+      auto fetch = [&](int s0, double* d0, double* d1, double (*b)[NTL]) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
           const int i = (s0 + u) * 4 + lr;
@@ -273,27 +263,27 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
           const double* Tr = Tt + static_cast<long long>(i) * nr;
           d0[u] = (iin && j0 < nr) ? Tr[j0] : 0.0;
           d1[u] = (iin && two && j1 < nr) ? Tr[j1] : 0.0;
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) b[u][n] = iin ? wb[static_cast<long long>(i) * R + n * 16] : 0.0;
         }
       };
-      fetch(0, a0c, a1c);
+      fetch(0, a0c, a1c, bc);
       for (int s0 = 0; s0 < nsteps; s0 += PF) {
-        if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n);
+        if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-          const int i = (s0 + u) * 4 + lr;
-          const bool iin = i < k;
-          const double* wr = w + (iin ? i : 0) * LD + lc;
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
-            const double b = iin ? wr[n * 16] : 0.0;
-            acc[0][n] = mfma(a0c[u], b, acc[0][n]);
-            if (two) acc[1][n] = mfma(a1c[u], b, acc[1][n]);
+            acc[0][n] = mfma(a0c[u], bc[u][n], acc[0][n]);
+            if (two) acc[1][n] = mfma(a1c[u], bc[u][n], acc[1][n]);
           }
         }
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
           a0c[u] = a0n[u];
           a1c[u] = a1n[u];
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
         }
       }
 #pragma unroll
@@ -314,13 +304,15 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
         }
       }
     }
+    const double* wrow = win + static_cast<long long>(tk.out_row[o]) * R + c0;
     for (int e = threadIdx.x; e < k * NT; e += 256) {
       const int i = e / NT, c = e % NT;
       double* dst = acc_l + static_cast<int>(skel[i]) * LD + c;
+      const double val = wrow[static_cast<long long>(i) * R + c];
       if (o == 0)
-        *dst = w[i * LD + c];
+        *dst = val;
       else
-        *dst += w[i * LD + c];
+        *dst += val;
     }
     __syncthreads();
   }
@@ -594,10 +586,11 @@ static hipError_t launch_level_class(const sht_plan_s* P, int step, const Launch
   if (cnt == 0) return hipSuccess;
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK, k = lc.maxk;
-  // LDS rows per column: synthesis K, transposed K + 2k; use 32 columns while that stays
-  // within 80 KiB (two work-groups per CU), else 16.
-  const long long rows = transpose ? K + 2LL * k : K;
-  const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
+  // LDS rows per column: K (the task's input block); use 32 columns while that stays
+  // within 100 KiB, else 16.
+  (void)k;
+  const long long rows = K;
+  const int NT = (R % 32 == 0 && rows * 34 * 8 <= 100 * 1024) ? 32 : 16;
   if (rows * 18 * 8 + 4LL * K + 16 > 160 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
@@ -613,7 +606,7 @@ static hipError_t launch_level_class(const sht_plan_s* P, int step, const Launch
       hipLaunchKernelGGL(k_level_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R, io);
     }
   } else {
-    const size_t lds = static_cast<size_t>(K + 2 * k) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
+    const size_t lds = static_cast<size_t>(K) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
     if (NT == 32) {
       if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_trans_mfma<32>), lds)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_level_trans_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R, io);
