@@ -115,9 +115,11 @@ class DeviceScope {
 int check_call(const sht_plan_s* P, int precision, const void* a, const void* b, int F, void* ws,
                size_t wsb) {
   if (!P || !a || !b || F < 1 || !ws) return SHT_EINVAL;
-  if (precision != SHT_FP64) return precision == SHT_SPLIT32 || precision == SHT_FP32
-                                        ? SHT_EUNSUPPORTED
-                                        : SHT_EINVAL;
+  if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
+  // the split and FP32 variants run on the matrix-core kernels only (R a multiple of 16), and
+  // the transposed final stage keeps at most 384 skeleton rows per task in registers
+  if (precision != SHT_FP64 && (!mfma_ok(field_width(P, F)) || P->final_maxk > 192))
+    return SHT_EUNSUPPORTED;
   if (reinterpret_cast<uintptr_t>(a) % 16 || reinterpret_cast<uintptr_t>(b) % 16) return SHT_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return SHT_EINVAL;
   if (wsb < ws_bytes(P, F)) return SHT_EINVAL;
@@ -186,6 +188,7 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const std::string fs = fsuffix(F);
@@ -217,6 +220,7 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);

@@ -1,20 +1,31 @@
-// Butterfly apply on the FP64 matrix cores (v_mfma_f64_16x16x4f64), used when the
-// number of R columns is a multiple of 16, i.e. many fields at once.
+// Butterfly apply on the matrix cores, used when the number of R columns is a multiple of
+// 16, i.e. many fields at once.  Three arithmetic variants share the kernels:
+//
+//  * FP64: v_mfma_f64_16x16x4f64.
+//  * split: every FP64 operand x is cut into x1 + x2 where x1 keeps the top bits on a grid
+//    common to its row (factors) or column (vectors), |x1| <= 2^10 grid units, and x2 =
+//    fp32(x - x1).  The product sum a1 b1 is exact in FP32 as long as at most 16 products
+//    are chained (2^20 per product, 2^24 per FP32 significand), so it runs on
+//    v_mfma_f32_16x16x4f32 without rounding and is added into an FP64 accumulator every
+//    four K-steps; the three correction products a1 b2 + a2 b1 + a2 b2 (2^-10 of the
+//    result and smaller) are accumulated in FP32 for one K-step and then added into the
+//    FP64 accumulator, which keeps their rounding near 2^-34 of the result.  Factor slices
+//    are prepared once per plan; vector slices are cut on the fly from per-task, per-column
+//    scales.
+//  * FP32: plain v_mfma_f32_16x16x4f32 on fp32(a), fp32(b), FP32 accumulation.
 //
 // Each interpolation is a small GEMM with a gathered operand: out = in[skel] + T in[red]
 // (synthesis) or in = sum_o scatter(T_o^T w_o, w_o) (transposed).  A work-group takes one
-// task and NT columns.  It first stages the task's vector rows for those columns in LDS with
-// coalesced loads (all in flight at once), then every wave runs MFMAs on pairs of 16-row
-// tiles: the factor fragments (A) stream from global memory in the order the plan packed
-// them (a stored column is contiguous, so 16 lanes read 128 consecutive bytes), the vector
-// fragments (B) come from LDS through the skeleton / redundant index lists.
-//
+// task and NT columns; every wave runs pairs of 16-row tiles with the factor fragments (A)
+// fetched four K-steps ahead from global memory (a stored column is contiguous, so 16 lanes
+// read consecutive words) and the vector fragments (B) from LDS or global memory.
 // Work-groups are numbered so that all column blocks of one task land on the same XCD
-// (work-group ids are dealt round-robin over the 8 XCDs): the factor matrix is then read
-// from HBM once and served to the other column blocks by that XCD's L2.
+// (ids are dealt round-robin over the 8 XCDs): the factor block is read from HBM once and
+// served to the other column blocks from that XCD's L2.
 //
-// MFMA f64 16x16x4 register layout (checked on gfx950): A[i][k] in lane i + 16k, B[k][j]
-// in lane j + 16k, and D[4v + lane/16][lane%16] in accumulator element v.
+// Register layouts (checked on gfx950): for both 16x16x4 shapes A[i][k] sits in lane
+// i + 16k and B[k][j] in lane j + 16k; the FP64 result D[4v + lane/16][lane%16] is in
+// element v, the FP32 result D[4(lane/16) + v][lane%16].
 #include <algorithm>
 
 #include "sht_internal.h"
@@ -24,14 +35,147 @@ namespace sht {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcd = 8;
+constexpr int kSliceBits = 10;  // |x1| <= 2^10 units of the row / column grid
 
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+enum { P64 = 0, PSPLIT = 1, P32 = 2 };
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
-__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+// Row of the 16x16 tile held in accumulator element v of a lane with lane/16 = lr.
+template <int PREC>
+__device__ __forceinline__ int drow(int v, int lr) { return PREC == P64 ? 4 * v + lr : 4 * lr + v; }
+
+// ---------------------------------------------------------------- operands and accumulators
+struct FacPtr {
+  const double* d;  // FP64 entries
+  const float* hi;  // split: leading slice, row-aligned
+  const float* lo;  // split: fp32 remainder
+};
+
+template <int PREC> struct AFrag;
+template <> struct AFrag<P64> { double a; };
+template <> struct AFrag<PSPLIT> { float a1, a2; };
+template <> struct AFrag<P32> { float a; };
+
+template <int PREC>
+__device__ __forceinline__ AFrag<PREC> load_a(const FacPtr& f, long long i, bool ok);
+template <>
+__device__ __forceinline__ AFrag<P64> load_a<P64>(const FacPtr& f, long long i, bool ok) {
+  return {ok ? f.d[i] : 0.0};
+}
+template <>
+__device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok) {
+  return {ok ? f.hi[i] : 0.0f, ok ? f.lo[i] : 0.0f};
+}
+template <>
+__device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok) {
+  return {ok ? f.hi[i] + f.lo[i] : 0.0f};
+}
+
+template <int PREC> struct BFrag;
+template <> struct BFrag<P64> { double b; };
+template <> struct BFrag<PSPLIT> { float b1, b2; };
+template <> struct BFrag<P32> { float b; };
+
+// sh = kSliceBits - e for the column's max |x| < 2^e (0 for an all-zero column); the
+// leading slice is x1 = 2^-sh rint(2^sh x), exact (ldexp, so no scale can overflow).
+template <int PREC>
+__device__ __forceinline__ BFrag<PREC> make_b(double x, int sh);
+template <>
+__device__ __forceinline__ BFrag<P64> make_b<P64>(double x, int) { return {x}; }
+template <>
+__device__ __forceinline__ BFrag<PSPLIT> make_b<PSPLIT>(double x, int sh) {
+  const double x1 = ldexp(rint(ldexp(x, sh)), -sh);
+  return {static_cast<float>(x1), static_cast<float>(x - x1)};
+}
+template <>
+__device__ __forceinline__ BFrag<P32> make_b<P32>(double x, int) { return {static_cast<float>(x)}; }
+
+template <int PREC> struct Acc;
+template <>
+struct Acc<P64> {
+  d4 v;
+  __device__ void zero() { v = d4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ void set(int e, double x) { v[e] = x; }
+  __device__ void step(const AFrag<P64>& a, const BFrag<P64>& b) { v = mfma64(a.a, b.b, v); }
+  __device__ void flush_step() {}
+  __device__ void flush() {}
+  __device__ double get(int e) const { return v[e]; }
+};
+template <>
+struct Acc<PSPLIT> {
+  d4 hi;
+  f4 ex, cr;
+  __device__ void zero() {
+    hi = d4{0.0, 0.0, 0.0, 0.0};
+    ex = f4{0.f, 0.f, 0.f, 0.f};
+    cr = ex;
+  }
+  __device__ void set(int e, double x) { hi[e] = x; }
+  __device__ void step(const AFrag<PSPLIT>& a, const BFrag<PSPLIT>& b) {
+    ex = mfma32(a.a1, b.b1, ex);  // exact
+    cr = mfma32(a.a1, b.b2, cr);
+    cr = mfma32(a.a2, b.b1, cr);
+    cr = mfma32(a.a2, b.b2, cr);
+  }
+  // corrections: after every K-step
+  __device__ void flush_step() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(cr[e]);
+    cr = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  // exact leading products: at most every four K-steps
+  __device__ void flush() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(ex[e]);
+    ex = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ double get(int e) const {
+    return hi[e] + static_cast<double>(ex[e]) + static_cast<double>(cr[e]);
+  }
+};
+template <>
+struct Acc<P32> {
+  d4 base;
+  f4 v;
+  __device__ void zero() {
+    base = d4{0.0, 0.0, 0.0, 0.0};
+    v = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ void set(int e, double x) { base[e] = x; }
+  __device__ void step(const AFrag<P32>& a, const BFrag<P32>& b) { v = mfma32(a.a, b.b, v); }
+  __device__ void flush_step() {}
+  __device__ void flush() {}
+  __device__ double get(int e) const { return base[e] + static_cast<double>(v[e]); }
+};
+
+// Per-column slice shifts of a rows x NT block: sh[c] = kSliceBits - e, max |x| < 2^e.
+// fetch(r, c) returns the FP64 entry.  All 256 threads take part; red must hold 256 doubles.
+template <int NT, typename Fetch>
+__device__ void column_scales(int rows, Fetch&& fetch, double* red, int* sc) {
+  constexpr int GROUPS = 256 / NT;
+  const int c = threadIdx.x % NT, g = threadIdx.x / NT;
+  double mx = 0.0;
+  for (int r = g; r < rows; r += GROUPS) mx = fmax(mx, fabs(fetch(r, c)));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  if (threadIdx.x < NT) {
+    double m = 0.0;
+    for (int q = 0; q < GROUPS; ++q) m = fmax(m, red[q * NT + threadIdx.x]);
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+    sc[threadIdx.x] = m > 0.0 ? kSliceBits - e : 0;
+  }
+  __syncthreads();
+}
 
 // (task, column block) of this work-group under the XCD-aware numbering; false if padding.
 __device__ __forceinline__ bool xcd_map(long long ntasks, int nblk, long long& task, int& blk) {
@@ -61,50 +205,52 @@ struct CoefIO {
   int l, kind;
 };
 
-// Visits the K x NT block of a leaf task (rows j of pair mp starting at column j0; local
-// columns c of the NT-column block c0) in an order where consecutive threads touch
-// consecutive degrees of one (field, sign): fn(j, c, position or -1 if no such entry).
+// Position in the coefficient array of row j, local column c of a leaf block (-1: no such
+// entry, -2: the imaginary part at m = 0 of a real field).
+__device__ __forceinline__ long long leaf_pos(const CoefIO& io, int m, int p, int j0, int j, long long col) {
+  const int k = m + p + 2 * (j0 + j);
+  const int cc = static_cast<int>(col & 1);
+  if (io.kind == SHT_COMPLEX) {
+    const int f = static_cast<int>(col >> 2), s = static_cast<int>((col >> 1) & 1);
+    return (m == 0 && s == 1) ? -1 : coeff_pos(io.l, SHT_COMPLEX, io.ncoef, f, m, s, k, cc);
+  }
+  const int f = static_cast<int>(col >> 1);
+  return (m == 0 && cc == 1) ? -2 : coeff_pos(io.l, SHT_REAL, io.ncoef, f, m, 0, k, cc);
+}
+
+// Visits the K x NT block of a leaf task in an order where consecutive threads touch
+// consecutive degrees of one (field, sign): fn(j, c, position).
 template <int NT, typename Fn>
-__device__ __forceinline__ void for_leaf_block(const CoefIO& io, int mp_m, int mp_p, int j0, int K,
+__device__ __forceinline__ void for_leaf_block(const CoefIO& io, int m, int p, int j0, int K,
                                                long long c0, Fn&& fn) {
   for (int e = threadIdx.x; e < K * NT; e += 256) {
     const int cc = e & 1;
     const int j = (e >> 1) % K;
-    const int g = (e >> 1) / K;  // (field, sign) group for complex, field for real
-    const int c = g * 2 + cc;
-    const int col = static_cast<int>(c0) + c;
-    const int k = mp_m + mp_p + 2 * (j0 + j);
-    long long pos;
-    if (io.kind == SHT_COMPLEX) {
-      const int f = col >> 2, s = (col >> 1) & 1;
-      pos = (mp_m == 0 && s == 1) ? -1 : coeff_pos(io.l, SHT_COMPLEX, io.ncoef, f, mp_m, s, k, cc);
-    } else {
-      const int f = col >> 1;
-      pos = (mp_m == 0 && cc == 1) ? -2 : coeff_pos(io.l, SHT_REAL, io.ncoef, f, mp_m, 0, k, cc);
-    }
-    fn(j, c, pos);
+    const int c = ((e >> 1) / K) * 2 + cc;
+    fn(j, c, leaf_pos(io, m, p, j0, j, c0 + c));
   }
 }
 
 // ------------------------------------------------------------------- level, synthesis
-template <int NT>
+template <int NT, int PREC>
 __global__ void __launch_bounds__(256)
-k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk,
-                   const double* __restrict__ fac, const uint16_t* __restrict__ idx,
-                   const double* __restrict__ in, double* __restrict__ out, int R, CoefIO io) {
+k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const uint16_t* __restrict__ idx, const double* __restrict__ in,
+                   double* __restrict__ out, int R, CoefIO io) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   extern __shared__ double lds[];
+  __shared__ double red_s[256];
+  __shared__ int colsc[NT];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
   const LevelTask tk = tasks[ti];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
-  double* xs = lds;                                              // K x LD
-  uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * LD);      // [skel0 red0 skel1 red1]
+  double* xs = lds;                                          // K x LD
+  uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * LD);  // [skel0 red0 skel1 red1]
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
-  const int nidx = (k0 > 0 ? K : 0) + (k1 > 0 ? K : 0);
   if (io.coeff && tk.mp >= 0) {
     const PairDesc pd = io.pairs[tk.mp];
     const double* cf = io.coeff;
@@ -119,19 +265,20 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
       xs[row * LD + 2 * c2 + 1] = v.y;
     }
   }
-  {
-    if (k0 > 0)
-      for (int e = threadIdx.x; e < K; e += 256) ix[e] = idx[tk.idx[0] + e];
-    if (k1 > 0)
-      for (int e = threadIdx.x; e < K; e += 256) ix[(k0 > 0 ? K : 0) + e] = idx[tk.idx[1] + e];
-  }
-  (void)nidx;
+  if (k0 > 0)
+    for (int e = threadIdx.x; e < K; e += 256) ix[e] = idx[tk.idx[0] + e];
+  if (k1 > 0)
+    for (int e = threadIdx.x; e < K; e += 256) ix[(k0 > 0 ? K : 0) + e] = idx[tk.idx[1] + e];
   __syncthreads();
+  if (PREC == PSPLIT)
+    column_scales<NT>(K, [&](int r, int c) { return xs[r * LD + c]; }, red_s, colsc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
+  int bsc[NTL];
+#pragma unroll
+  for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[n * 16 + lc] : 0;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
-  // pairs of row tiles: output 0 tiles, then output 1 tiles
-  const int np0 = (nm0 + 1) >> 1, np1 = (nm1 + 1) >> 1;
+  const int np0 = (nm0 + 1) >> 1, np1 = (nm1 + 1) >> 1;  // pairs of row tiles per output
   for (int q = wave; q < np0 + np1; q += 4) {
     const int o = q < np0 ? 0 : 1;
     const int mt0 = 2 * (o ? q - np0 : q);
@@ -139,34 +286,34 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
     const int nr = K - k;
     const uint16_t* skel = ix + (o && k0 > 0 ? K : 0);
     const uint16_t* red = skel + k;
-    const double* T = fac + tk.fac[o];
+    const long long toff = tk.fac[o];
     const bool two = mt0 + 1 < (o ? nm1 : nm0);
-    d4 acc[2][NTL];
+    Acc<PREC> acc[2][NTL];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
+        acc[u][n].zero();
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = (mt0 + u) * 16 + 4 * v + lr;
-          acc[u][n][v] = row < k ? xs[skel[row] * LD + n * 16 + lc] : 0.0;
+          const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
+          acc[u][n].set(v, row < k ? xs[skel[row] * LD + n * 16 + lc] : 0.0);
         }
       }
     }
     const int i0 = mt0 * 16 + lc, i1 = i0 + 16;
-    // factor fragments are fetched PF K-steps ahead (double-buffered in registers) so the
-    // global-load latency overlaps the MFMAs of the previous steps
+    // factor fragments are fetched PF K-steps ahead (double-buffered in registers)
     constexpr int PF = 4;
     const int nsteps = (nr + 3) >> 2;
-    double a0c[PF], a1c[PF], a0n[PF], a1n[PF];
-    auto fetch = [&](int s0, double* d0, double* d1) {
+    AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
+    auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
         const bool kin = kk < nr;
-        const double* Tc = T + static_cast<long long>(kk) * k;
-        d0[u] = (kin && i0 < k) ? Tc[i0] : 0.0;
-        d1[u] = (kin && two && i1 < k) ? Tc[i1] : 0.0;
+        const long long base = toff + static_cast<long long>(kk) * k;
+        d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k);
+        d1[u] = load_a<PREC>(fp, base + i1, kin && two && i1 < k);
       }
     };
     fetch(0, a0c, a1c);
@@ -179,10 +326,20 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
         const double* xr = xs + (kin ? red[kk] : 0) * LD + lc;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          const double b = kin ? xr[n * 16] : 0.0;
-          acc[0][n] = mfma(a0c[u], b, acc[0][n]);
-          if (two) acc[1][n] = mfma(a1c[u], b, acc[1][n]);
+          const BFrag<PREC> b = make_b<PREC>(kin ? xr[n * 16] : 0.0, bsc[n]);
+          acc[0][n].step(a0c[u], b);
+          if (two) acc[1][n].step(a1c[u], b);
         }
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) {
+          acc[0][n].flush_step();
+          acc[1][n].flush_step();
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NTL; ++n) {
+        acc[0][n].flush();
+        acc[1][n].flush();
       }
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
@@ -195,10 +352,10 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = (mt0 + u) * 16 + 4 * v + lr;
+        const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
         if (row < k) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n * 16] = acc[u][n][v];
+          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n * 16] = acc[u][n].get(v);
         }
       }
     }
@@ -211,14 +368,16 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 // the factor fragments).  Output block o contributes T_o^T w_o at rows red_o and w_o at
 // rows skel_o (assigned for o = 0, added for o = 1; every row gets exactly one term per
 // block).
-template <int NT>
+template <int NT, int PREC>
 __global__ void __launch_bounds__(256)
-k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk,
-                   const double* __restrict__ fac_t, const uint16_t* __restrict__ idx,
-                   const double* __restrict__ win, double* __restrict__ xout, int R, CoefIO io) {
+k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const uint16_t* __restrict__ idx, const double* __restrict__ win,
+                   double* __restrict__ xout, int R, CoefIO io) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   extern __shared__ double lds[];
+  __shared__ double red_s[256];
+  __shared__ int colsc[2][NT];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
@@ -231,6 +390,13 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   uint16_t* ix = reinterpret_cast<uint16_t*>(acc_l + K * LD);  // [skel0 red0 skel1 red1]
   for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
+  if (PREC == PSPLIT) {
+    for (int o = 0; o < nouts; ++o) {
+      const double* wrow = win + static_cast<long long>(tk.out_row[o]) * R + c0;
+      column_scales<NT>(o ? k1 : k0, [&](int r, int c) { return wrow[static_cast<long long>(r) * R + c]; },
+                        red_s, colsc[o]);
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
@@ -239,30 +405,34 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
     const int nr = K - k;
     const uint16_t* skel = ix + o * K;
     const uint16_t* red = skel + k;
-    const double* Tt = fac_t + tk.fac[o];  // nr x k column-major
+    const long long toff = tk.fac[o];  // T^T: nr x k column-major
     const double* wb = win + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
+    int bsc[NTL];
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[o][n * 16 + lc] : 0;
     const int nm = (nr + 15) >> 4;
     const int np = (nm + 1) >> 1;
     for (int q = wave; q < np; q += 4) {
       const int mt0 = 2 * q;
       const bool two = mt0 + 1 < nm;
-      d4 acc[2][NTL];
+      Acc<PREC> acc[2][NTL];
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) acc[u][n] = zero4();
+        for (int n = 0; n < NTL; ++n) acc[u][n].zero();
       const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
       constexpr int PF = 4;
       const int nsteps = (k + 3) >> 2;
-      double a0c[PF], a1c[PF], a0n[PF], a1n[PF], bc[PF][NTL], bn[PF][NTL];
-      auto fetch = [&](int s0, double* d0, double* d1, double (*b)[NTL]) {
+      AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
+      double bc[PF][NTL], bn[PF][NTL];
+      auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, double (*b)[NTL]) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
           const int i = (s0 + u) * 4 + lr;
           const bool iin = i < k;
-          const double* Tr = Tt + static_cast<long long>(i) * nr;
-          d0[u] = (iin && j0 < nr) ? Tr[j0] : 0.0;
-          d1[u] = (iin && two && j1 < nr) ? Tr[j1] : 0.0;
+          const long long base = toff + static_cast<long long>(i) * nr;
+          d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr);
+          d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr);
 #pragma unroll
           for (int n = 0; n < NTL; ++n) b[u][n] = iin ? wb[static_cast<long long>(i) * R + n * 16] : 0.0;
         }
@@ -274,9 +444,20 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
         for (int u = 0; u < PF; ++u) {
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
-            acc[0][n] = mfma(a0c[u], bc[u][n], acc[0][n]);
-            if (two) acc[1][n] = mfma(a1c[u], bc[u][n], acc[1][n]);
+            const BFrag<PREC> b = make_b<PREC>(bc[u][n], bsc[n]);
+            acc[0][n].step(a0c[u], b);
+            if (two) acc[1][n].step(a1c[u], b);
           }
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) {
+            acc[0][n].flush_step();
+            acc[1][n].flush_step();
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) {
+          acc[0][n].flush();
+          acc[1][n].flush();
         }
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -290,15 +471,15 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
       for (int u = 0; u < 2; ++u) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int j = (mt0 + u) * 16 + 4 * v + lr;
+          const int j = (mt0 + u) * 16 + drow<PREC>(v, lr);
           if (j < nr) {
             double* dst = acc_l + static_cast<int>(red[j]) * LD + lc;
 #pragma unroll
             for (int n = 0; n < NTL; ++n) {
               if (o == 0)
-                dst[n * 16] = acc[u][n][v];
+                dst[n * 16] = acc[u][n].get(v);
               else
-                dst[n * 16] += acc[u][n][v];
+                dst[n * 16] += acc[u][n].get(v);
             }
           }
         }
@@ -319,12 +500,13 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   if (io.coeff && tk.mp >= 0) {
     const PairDesc pd = io.pairs[tk.mp];
     double* cf = io.coeff;
-    for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0, [&](int j, int c, long long pos) {
+    const int j0 = tk.in_row - pd.in_base;
+    for_leaf_block<NT>(io, pd.m, pd.p, j0, K, c0, [&](int j, int c, long long pos) {
       if (pos >= 0)
         cf[pos] = acc_l[j * LD + c];
       else if (pos == -2)  // imaginary part at m = 0 of a real field
         cf[coeff_pos(io.l, SHT_REAL, io.ncoef, static_cast<int>((c0 + c) >> 1), 0, 0,
-                     pd.p + 2 * (tk.in_row - pd.in_base + j), 1)] = 0.0;
+                     pd.p + 2 * (j0 + j), 1)] = 0.0;
     });
     return;
   }
@@ -337,16 +519,17 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 }
 
 // ------------------------------------------------------------------- final, synthesis
-// E = S_0 v_0, O = S_1 v_1 on one pair of 16-row tiles; g(+-x) = (E +- O) / D.
-template <int NT>
+// E = S_0 v_0, O = S_1 v_1 on one 16-row tile; g(+-x) = (E +- O) / D.
+template <int NT, int PREC>
 __global__ void __launch_bounds__(256)
-k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk,
-                   const double* __restrict__ fac, const double* __restrict__ v0buf,
-                   const double* __restrict__ v1buf, const double* __restrict__ invD,
-                   double* __restrict__ Y, int l, int R) {
+k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const double* __restrict__ v0buf, const double* __restrict__ v1buf,
+                   const double* __restrict__ invD, double* __restrict__ Y, int l, int R) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   extern __shared__ double lds[];
+  __shared__ double red_s[256];
+  __shared__ int colsc[2][NT];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
@@ -368,33 +551,40 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
     }
   }
   __syncthreads();
+  if (PREC == PSPLIT) {
+    column_scales<NT>(k0, [&](int r, int c) { return w0[r * LD + c]; }, red_s, colsc[0]);
+    column_scales<NT>(k1, [&](int r, int c) { return w1[r * LD + c]; }, red_s, colsc[1]);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
-  const double* S0 = fac + ft.fac[0];
-  const double* S1 = fac + ft.fac[1];
+  int bsc[2][NTL];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) bsc[p][n] = PREC == PSPLIT ? colsc[p][n * 16 + lc] : 0;
   const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   const int nm = (h + 15) >> 4;
   for (int mt = wave; mt < nm; mt += 4) {
-    d4 E[NTL], O[NTL];
+    Acc<PREC> E[NTL], O[NTL];
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
-      E[n] = zero4();
-      O[n] = zero4();
+      E[n].zero();
+      O[n].zero();
     }
     const int i = mt * 16 + lc;
     const bool iin = i < h;
     // both parities in one prefetched loop: step s < n0 feeds E, the rest feed O
     constexpr int PF = 4;
     const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 + n1;
-    double ac[PF], an[PF];
-    auto fetch = [&](int s0, double* d) {
+    AFrag<PREC> ac[PF], an[PF];
+    auto fetch = [&](int s0, AFrag<PREC>* d) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int st = s0 + u;
         const bool odd = st >= n0;
         const int a = (odd ? st - n0 : st) * 4 + lr;
         const bool ain = st < nsteps && a < (odd ? k1 : k0);
-        d[u] = (ain && iin) ? (odd ? S1 : S0)[static_cast<long long>(a) * h + i] : 0.0;
+        d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin);
       }
     };
     fetch(0, ac);
@@ -410,18 +600,27 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
         const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc;
         if (!odd) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) E[n] = mfma(ac[u], ain ? wr[n * 16] : 0.0, E[n]);
+          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], make_b<PREC>(ain ? wr[n * 16] : 0.0, bsc[0][n]));
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) E[n].flush_step();
         } else {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) O[n] = mfma(ac[u], ain ? wr[n * 16] : 0.0, O[n]);
+          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], make_b<PREC>(ain ? wr[n * 16] : 0.0, bsc[1][n]));
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) O[n].flush_step();
         }
+      }
+#pragma unroll
+      for (int n = 0; n < NTL; ++n) {
+        E[n].flush();
+        O[n].flush();
       }
 #pragma unroll
       for (int u = 0; u < PF; ++u) ac[u] = an[u];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ii = mt * 16 + 4 * v + lr;
+      const int ii = mt * 16 + drow<PREC>(v, lr);
       if (ii < h) {
         const int row = ft.row0 + ii;
         const double s = invD[row];
@@ -429,8 +628,9 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
         double* ym = Y + (ybase + l - 1 - row) * R + c0 + lc;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          yp[n * 16] = (E[n][v] + O[n][v]) * s;
-          ym[n * 16] = (E[n][v] - O[n][v]) * s;
+          const double e = E[n].get(v), od = O[n].get(v);
+          yp[n * 16] = (e + od) * s;
+          ym[n * 16] = (e - od) * s;
         }
       }
     }
@@ -440,16 +640,17 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
 // ------------------------------------------------------------------ final, transposed
 // v_p = S_p^T (half * scale * (G(+x) +- G(-x))): the folded rows are built in LDS chunk by
 // chunk; each wave keeps the accumulators of its row tiles across the chunks.
-template <int NT, int ICH>
+template <int NT, int ICH, int PREC>
 __global__ void __launch_bounds__(256)
-k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk,
-                   const double* __restrict__ fac_t, const double* __restrict__ Yin,
-                   const double* __restrict__ scale, double half, double* __restrict__ v0buf,
-                   double* __restrict__ v1buf, int l, int R) {
+k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const double* __restrict__ Yin, const double* __restrict__ scale, double half,
+                   double* __restrict__ v0buf, double* __restrict__ v1buf, int l, int R) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   constexpr int MAXT = 6;  // row tiles per wave (k0 + k1 <= 384)
   __shared__ double eo[2][ICH * LD];
+  __shared__ double red_s[256];
+  __shared__ int colsc[2][NT];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
@@ -461,11 +662,11 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
-  d4 acc[MAXT][NTL];
+  Acc<PREC> acc[MAXT][NTL];
 #pragma unroll
   for (int u = 0; u < MAXT; ++u)
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) acc[u][n] = zero4();
+    for (int n = 0; n < NTL; ++n) acc[u][n].zero();
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     __syncthreads();
@@ -479,6 +680,10 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
       eo[1][i * LD + c] = (gp - gm) * sc;
     }
     __syncthreads();
+    if (PREC == PSPLIT) {
+      column_scales<NT>(ih, [&](int r, int c) { return eo[0][r * LD + c]; }, red_s, colsc[0]);
+      column_scales<NT>(ih, [&](int r, int c) { return eo[1][r * LD + c]; }, red_s, colsc[1]);
+    }
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
       const int q = wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
@@ -486,16 +691,19 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
       const int p = q < nm0 ? 0 : 1;
       const int k = p ? k1 : k0;
       const int a = (p ? q - nm0 : q) * 16 + lc;
-      const double* St = fac_t + ft.fac[p];  // k x h column-major
+      const long long soff = ft.fac[p];  // S^T: k x h column-major
       const double* src = eo[p];
+      int bsc[NTL];
+#pragma unroll
+      for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[p][n * 16 + lc] : 0;
       constexpr int PF = 4;
       const int nsteps = (ih + 3) >> 2;
-      double ac[PF], an[PF];
-      auto fetch = [&](int s0, double* d) {
+      AFrag<PREC> ac[PF], an[PF];
+      auto fetch = [&](int s0, AFrag<PREC>* d) {
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
-          d[w] = (i < ih && a < k) ? St[static_cast<long long>(i0 + i) * k + a] : 0.0;
+          d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k);
         }
       };
       fetch(0, ac);
@@ -507,8 +715,12 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
           const bool iin = i < ih;
           const double* er = src + (iin ? i : 0) * LD + lc;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n] = mfma(ac[w], iin ? er[n * 16] : 0.0, acc[u][n]);
+          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], make_b<PREC>(iin ? er[n * 16] : 0.0, bsc[n]));
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) acc[u][n].flush_step();
         }
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) acc[u][n].flush();
 #pragma unroll
         for (int w = 0; w < PF; ++w) ac[w] = an[w];
       }
@@ -524,15 +736,16 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
     double* vout = V + static_cast<long long>(ft.in_row[p]) * R + c0 + lc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int a = mt * 16 + 4 * v + lr;
+      const int a = mt * 16 + drow<PREC>(v, lr);
       if (a < k) {
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) vout[static_cast<long long>(a) * R + n * 16] = acc[u][n][v];
+        for (int n = 0; n < NTL; ++n) vout[static_cast<long long>(a) * R + n * 16] = acc[u][n].get(v);
       }
     }
   }
 }
 
+// ------------------------------------------------------------------ factor preparation
 __global__ void k_transpose_blocks(const double* __restrict__ fac, double* __restrict__ fac_t,
                                    const FactorBlock* __restrict__ blocks) {
   const FactorBlock b = blocks[blockIdx.x];
@@ -543,9 +756,109 @@ __global__ void k_transpose_blocks(const double* __restrict__ fac, double* __res
   }
 }
 
+// Row-aligned split of every stored matrix (column-major, `rows` x `cols`; transposed: the
+// stored block is cols x rows): hi = leading slice on the row's grid, lo = fp32 remainder.
+__global__ void k_split_rows(const double* __restrict__ src, float* __restrict__ hi,
+                             float* __restrict__ lo, const FactorBlock* __restrict__ blocks,
+                             int transposed) {
+  const FactorBlock b = blocks[blockIdx.x];
+  const int nrows = transposed ? b.cols : b.rows;
+  const int ncols = transposed ? b.rows : b.cols;
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    double mx = 0.0;
+    for (int c = 0; c < ncols; ++c) mx = fmax(mx, fabs(src[b.off + static_cast<long long>(c) * nrows + r]));
+    int e = 0;
+    if (mx > 0.0) (void)frexp(mx, &e);
+    const int sh = mx > 0.0 ? kSliceBits - e : 0;
+    for (int c = 0; c < ncols; ++c) {
+      const long long i = b.off + static_cast<long long>(c) * nrows + r;
+      const double x = src[i];
+      const double x1 = ldexp(rint(ldexp(x, sh)), -sh);
+      hi[i] = static_cast<float>(x1);
+      lo[i] = static_cast<float>(x - x1);
+    }
+  }
+}
+
 hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+FacPtr fac_ptr(const sht_plan_s* P, bool transposed) {
+  return transposed ? FacPtr{P->d.fac_t, P->d.fac_t_hi, P->d.fac_t_lo}
+                    : FacPtr{P->d.fac, P->d.fac_hi, P->d.fac_lo};
+}
+
+template <int PREC>
+hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, bool transpose,
+                       const double* in, double* out, int R, const CoefIO& io, hipStream_t s) {
+  const long long cnt = lc.cnt;
+  if (cnt == 0) return hipSuccess;
+  const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
+  const int K = lc.maxK;
+  // LDS holds the task's K x NT input block: 32 columns while that stays within 100 KiB
+  const int NT = (R % 32 == 0 && static_cast<long long>(K) * 34 * 8 <= 100 * 1024) ? 32 : 16;
+  if (static_cast<long long>(K) * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
+  const int nblk = R / NT;
+  const dim3 grid(xcd_grid(cnt, nblk));
+  const size_t lds = static_cast<size_t>(K) * (NT + 2) * 8 + 4 * static_cast<size_t>(K) + 16;
+  const FacPtr fp = fac_ptr(P, transpose);
+  hipError_t e;
+#define LEVEL_LAUNCH(KER)                                                                              \
+  do {                                                                                                 \
+    if ((e = allow_lds(reinterpret_cast<const void*>(&KER), lds)) != hipSuccess) return e;             \
+    hipLaunchKernelGGL(KER, grid, dim3(256), lds, s, tasks, cnt, nblk, fp, P->d.idx, in, out, R, io);  \
+  } while (0)
+  if (!transpose) {
+    if (NT == 32)
+      LEVEL_LAUNCH((k_level_synth_mfma<32, PREC>));
+    else
+      LEVEL_LAUNCH((k_level_synth_mfma<16, PREC>));
+  } else {
+    if (NT == 32)
+      LEVEL_LAUNCH((k_level_trans_mfma<32, PREC>));
+    else
+      LEVEL_LAUNCH((k_level_trans_mfma<16, PREC>));
+  }
+#undef LEVEL_LAUNCH
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t final_launch(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
+                        double* v0w, double* v1w, double* y, const double* yin, int R, bool adjoint,
+                        hipStream_t s) {
+  hipError_t e;
+  const FacPtr fp = fac_ptr(P, transpose);
+  if (!transpose) {
+    for (const LaunchClass& lc : P->final_classes) {
+      const long long cnt = lc.cnt;
+      const FinalTask* tasks = P->d.finals + lc.off;
+      const long long rows = 2LL * lc.maxk;
+      const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
+      const int nblk = R / NT;
+      const dim3 grid(xcd_grid(cnt, nblk));
+      const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 16;
+      if (NT == 32) {
+        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<32, PREC>), lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_final_synth_mfma<32, PREC>), grid, dim3(256), lds, s, tasks, cnt, nblk, fp, v0, v1, P->d.invD, y, P->l, R);
+      } else {
+        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<16, PREC>), lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_final_synth_mfma<16, PREC>), grid, dim3(256), lds, s, tasks, cnt, nblk, fp, v0, v1, P->d.invD, y, P->l, R);
+      }
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const long long cnt = P->n_final;
+  const double* scale = adjoint ? P->d.invD : P->d.D;
+  const double half = adjoint ? 1.0 : 0.5;
+  const int NT = 16;
+  const int nblk = R / NT;
+  const dim3 grid(xcd_grid(cnt, nblk));
+  hipLaunchKernelGGL((k_final_trans_mfma<16, 128, PREC>), grid, dim3(256), 0, s, P->d.finals, cnt, nblk, fp, yin, scale, half, v0w, v1w, P->l, R);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -562,97 +875,66 @@ hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock
   return hipSuccess;
 }
 
+hipError_t split_factors(sht_plan_s* P, hipStream_t s) {
+  if (P->d.fac_hi) return hipSuccess;
+  const size_t n = static_cast<size_t>(std::max<long long>(P->n_fac, 4));
+  float* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int b = 0; b < 4; ++b) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&bufs[b]), n * sizeof(float));
+    if (e != hipSuccess) {
+      for (int q = 0; q < b; ++q) (void)hipFree(bufs[q]);
+      return e;
+    }
+  }
+  for (long long b0 = 0; b0 < P->n_blocks; b0 += 1 << 20) {
+    const long long nb = std::min<long long>(1 << 20, P->n_blocks - b0);
+    hipLaunchKernelGGL(k_split_rows, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, P->d.fac, bufs[0],
+                       bufs[1], P->d.blocks + b0, 0);
+    hipLaunchKernelGGL(k_split_rows, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, P->d.fac_t,
+                       bufs[2], bufs[3], P->d.blocks + b0, 1);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    for (float* q : bufs) (void)hipFree(q);
+    return e;
+  }
+  P->d.fac_hi = bufs[0];
+  P->d.fac_lo = bufs[1];
+  P->d.fac_t_hi = bufs[2];
+  P->d.fac_t_lo = bufs[3];
+  P->stats.device_bytes += static_cast<long long>(4 * n * sizeof(float));
+  return hipSuccess;
+}
+
 bool mfma_ok(int R) { return R % 16 == 0; }
 
-static hipError_t launch_level_class(const sht_plan_s* P, int step, const LaunchClass& lc,
-                                     bool transpose, const double* in, double* out, int R,
-                                     const CoefIO& io, hipStream_t s);
-
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, hipStream_t s, double* coeff) {
+                             double* out, int R, int precision, hipStream_t s, double* coeff) {
   CoefIO io{coeff, P->d.pairs,
             P->kind == SHT_COMPLEX ? 4LL * P->l * P->l : 2LL * P->l * P->l + P->l, P->l, P->kind};
   for (const LaunchClass& lc : P->step_classes[step]) {
-    hipError_t e = launch_level_class(P, step, lc, transpose, in, out, R, io, s);
+    hipError_t e;
+    if (precision == SHT_SPLIT32)
+      e = level_class<PSPLIT>(P, step, lc, transpose, in, out, R, io, s);
+    else if (precision == SHT_FP32)
+      e = level_class<P32>(P, step, lc, transpose, in, out, R, io, s);
+    else
+      e = level_class<P64>(P, step, lc, transpose, in, out, R, io, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-static hipError_t launch_level_class(const sht_plan_s* P, int step, const LaunchClass& lc,
-                                     bool transpose, const double* in, double* out, int R,
-                                     const CoefIO& io, hipStream_t s) {
-  const long long cnt = lc.cnt;
-  if (cnt == 0) return hipSuccess;
-  const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
-  const int K = lc.maxK, k = lc.maxk;
-  // LDS rows per column: K (the task's input block); use 32 columns while that stays
-  // within 100 KiB, else 16.
-  (void)k;
-  const long long rows = K;
-  const int NT = (R % 32 == 0 && rows * 34 * 8 <= 100 * 1024) ? 32 : 16;
-  if (rows * 18 * 8 + 4LL * K + 16 > 160 * 1024) return hipErrorInvalidConfiguration;
-  const int nblk = R / NT;
-  const dim3 grid(xcd_grid(cnt, nblk));
-  const int LD = NT + 2;
-  hipError_t e;
-  if (!transpose) {
-    const size_t lds = static_cast<size_t>(K) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
-    if (NT == 32) {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_synth_mfma<32>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_synth_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R, io);
-    } else {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_synth_mfma<16>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, P->d.idx, in, out, R, io);
-    }
-  } else {
-    const size_t lds = static_cast<size_t>(K) * LD * 8 + 4 * static_cast<size_t>(K) + 16;
-    if (NT == 32) {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_trans_mfma<32>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_trans_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R, io);
-    } else {
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_level_trans_mfma<16>), lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_level_trans_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac_t, P->d.idx, in, out, R, io);
-    }
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
-                             bool adjoint, hipStream_t s) {
-  const long long total = P->n_final;
-  if (total == 0) return hipSuccess;
-  hipError_t e;
-  if (!transpose) {
-    for (const LaunchClass& lc : P->final_classes) {
-      const long long cnt = lc.cnt;
-      const FinalTask* tasks = P->d.finals + lc.off;
-      const long long rows = 2LL * lc.maxk;
-      const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
-      const int nblk = R / NT;
-      const dim3 grid(xcd_grid(cnt, nblk));
-      const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 16;
-      if (NT == 32) {
-        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<32>), lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_final_synth_mfma<32>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
-      } else {
-        if ((e = allow_lds(reinterpret_cast<const void*>(&k_final_synth_mfma<16>), lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_final_synth_mfma<16>, grid, dim3(256), lds, s, tasks, cnt, nblk, P->d.fac, v0, v1, P->d.invD, y, P->l, R);
-      }
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-  } else {
-    const long long cnt = total;
-    if (P->final_maxk > 6 * 16 * 4 / 2) return hipErrorInvalidValue;  // k0 + k1 <= 384
-    const double* scale = adjoint ? P->d.invD : P->d.D;
-    const double half = adjoint ? 1.0 : 0.5;
-    const int NT = 16;
-    const int nblk = R / NT;
-    const dim3 grid(xcd_grid(cnt, nblk));
-    hipLaunchKernelGGL((k_final_trans_mfma<16, 128>), grid, dim3(256), 0, s, P->d.finals, cnt, nblk, P->d.fac_t, yin, scale, half, v0w, v1w, P->l, R);
-  }
-  return hipGetLastError();
+                             int precision, bool adjoint, hipStream_t s) {
+  if (P->n_final == 0) return hipSuccess;
+  if (precision == SHT_SPLIT32)
+    return final_launch<PSPLIT>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
+  if (precision == SHT_FP32)
+    return final_launch<P32>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
+  return final_launch<P64>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
 }
 
 }  // namespace sht

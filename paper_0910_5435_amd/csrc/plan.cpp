@@ -463,7 +463,8 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e == hipSuccess)
     e = transpose_factors(P->d.fac, P->d.fac_t, dblocks, static_cast<long long>(fblocks.size()), nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (dblocks) (void)hipFree(dblocks);
+  P->d.blocks = dblocks;  // kept: the split copies are derived from it on first use
+  P->n_blocks = static_cast<long long>(fblocks.size());
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   P->stats.device_bytes =
       static_cast<long long>(2 * fac.size() * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
@@ -473,8 +474,9 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
 }
 
 void free_plan_device(sht_plan_s* P) {
-  void* ptrs[] = {P->d.fac,    P->d.fac_t, P->d.fac_hi, P->d.fac_lo, P->d.idx,    P->d.tasks,
-                  P->d.finals, P->d.pairs, P->d.invD,   P->d.D,      P->d.twiddle};
+  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hi, P->d.fac_lo, P->d.fac_t_hi,
+                  P->d.fac_t_lo, P->d.blocks, P->d.idx,    P->d.tasks,  P->d.finals,
+                  P->d.pairs,  P->d.invD,     P->d.D,      P->d.twiddle};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   P->d = DeviceFactors{};

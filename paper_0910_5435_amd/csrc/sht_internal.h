@@ -70,8 +70,11 @@ struct FactorBlock {
 struct DeviceFactors {
   double* fac = nullptr;       // T and S entries (FP64), column-major, read by synthesis
   double* fac_t = nullptr;     // the same matrices transposed (same offsets), read by analysis
-  float* fac_hi = nullptr;     // FP32 split copies (allocated on first split/fp32 use)
-  float* fac_lo = nullptr;
+  float* fac_hi = nullptr;     // split copies (first use of a split/FP32 transform): leading
+  float* fac_lo = nullptr;     // slice on each row's grid and the FP32 remainder, synthesis
+  float* fac_t_hi = nullptr;   // the same for the transposed copies
+  float* fac_t_lo = nullptr;
+  FactorBlock* blocks = nullptr;  // every stored matrix (offset, rows, cols)
   uint16_t* idx = nullptr;     // skel/red index lists
   LevelTask* tasks = nullptr;  // all level tasks, step by step
   FinalTask* finals = nullptr;
@@ -124,7 +127,7 @@ struct sht_plan_s {
   std::vector<int> n_cols, levels;      // per pair mp = 2m + p
   std::vector<int> in_base, v_base, v_rows;
   long long rows_in = 0, rows_v = 0, rows_y = 0;
-  long long n_fac = 0, n_fac_split = 0, n_idx = 0;
+  long long n_fac = 0, n_fac_split = 0, n_idx = 0, n_blocks = 0;
   std::vector<long long> step_off, step_cnt;  // level tasks per step (t = 0..Lmax)
   std::vector<int> step_maxK, step_maxk;      // largest input / output length per step
   std::vector<std::vector<sht::LaunchClass>> step_classes;
@@ -161,10 +164,10 @@ bool mfma_ok(int R);
 // coeff (leaf step only, may be null): read the leaf input from (synthesis) or write the
 // leaf output to (transposed) the caller's coefficient array instead of the row buffer.
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, hipStream_t s, double* coeff);
+                             double* out, int R, int precision, hipStream_t s, double* coeff);
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
-                             bool adjoint, hipStream_t s);
+                             int precision, bool adjoint, hipStream_t s);
 hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock* blocks,
                              long long nblocks, hipStream_t s);
 

@@ -147,3 +147,48 @@ def test_round_trip_gpu_only():
     back = P.analyze(P.synth(beta))
     err = _rel(back.cpu().numpy(), beta.cpu().numpy())
     assert err.max() < FP64_TOL
+
+
+# --------------------------------------------------------------------- precision variants
+# split: FP64 operands cut into an exactly-multiplied leading slice plus an FP32 remainder
+# on the FP32 matrix cores, accumulated in FP64 every four K-steps (gate 1e-9); FP32: plain
+# single precision (error reported, loose sanity bound only).
+SPLIT_TOL = 1e-9
+
+
+@pytest.mark.parametrize("l,C,F", [(64, 16, 4), (128, 32, 8), (256, 64, 16)])
+def test_split_precision_matches_oracle(l, C, F):
+    P = _plan(l, C, eps=1e-12)
+    beta = syn.coefficients(l, F, seed=0, power=1.5)
+    ref = oracle.synth(beta, l)
+    got = P.synth(_dev(beta), precision="split32").cpu().numpy()
+    es = _rel(got, ref)
+    g = syn.grid(l, F, seed=1)
+    ga = P.analyze(_dev(g), precision="split32").cpu().numpy()
+    ea = _rel(ga, oracle.analyze(g, l))
+    f32 = P.synth(_dev(beta), precision="fp32").cpu().numpy()
+    e32 = _rel(f32, ref)
+    print(f"split l={l} F={F}: synth {es.max():.2e} analysis {ea.max():.2e}; fp32 synth {e32.max():.2e}")
+    assert es.max() < SPLIT_TOL and ea.max() < SPLIT_TOL
+    assert e32.max() < 1e-4
+
+
+def test_split_precision_real_fields_and_adjoint():
+    l, C, F = 64, 16, 8
+    P = _plan(l, C, eps=1e-12, kind="real")
+    beta = syn.coefficients(l, F, seed=3, kind="real", power=1.5)
+    got = P.synth(_dev(beta), precision="split32").cpu().numpy()
+    assert _rel(got, oracle.synth(beta, l, kind="real")).max() < SPLIT_TOL
+    r = syn.grid(l, F, seed=4, kind="real")
+    adj = P.synth_adjoint(_dev(r), precision="split32").cpu().numpy()
+    assert _rel(adj, oracle.synth_adjoint(r, l, kind="real")).max() < SPLIT_TOL
+
+
+def test_split_precision_needs_matrix_core_widths():
+    from paper_0910_5435_amd import _lib
+
+    P = _plan(32, 8)
+    beta = _dev(syn.coefficients(32, 1, seed=0))
+    with pytest.raises(_lib.ShtError) as ei:
+        P.synth(beta, precision="split32")
+    assert ei.value.status == _lib.SHT_EUNSUPPORTED
