@@ -223,19 +223,20 @@ def analyze_orders(f, l, orders, kind="complex", grid="fft"):
     return out
 
 
-def synth_adjoint(r, l, kind="complex", grid="fft", direct=False):
+def synth_adjoint(r, l, kind="complex", grid="fft", direct=False, orders=None):
     """Adjoint of ``synth`` for the real inner products of its input and output.
 
     Complex fields: gamma_k^m = sum_i Pbar_k^{|m|}(x_i) sum_j r_ij e^{-i m phi_j}
     (the conjugate transpose).  Real fields (m >= 0 stored, beta^{-m} =
     conj(beta^m)): the same sum times 2 for m > 0, real part only at m = 0.
+    With ``orders`` (a list of |m|) only those orders are computed; the others are 0.
     """
     r = np.asarray(r)
     if r.ndim == 2:
         r = r[None]
     x, _ = gauss_legendre(2 * l)
     G = _fourier_coeffs(r.astype(np.complex128), l, grid, direct, normalize=False)
-    out = _coefficient_sums(G, l, np.ones_like(x), x, kind)
+    out = _coefficient_sums(G, l, np.ones_like(x), x, kind, orders)
     if kind == "real":
         out *= 2.0
         out[:, : 2 * l] = 0.5 * out[:, : 2 * l].real

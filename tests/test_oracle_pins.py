@@ -315,3 +315,35 @@ def test_subset_routines_agree_with_full():
         for k in range(abs(m), 2 * l):
             i = oracle.coeff_index(l, k, m)
             assert abs(part[0, i] - full[0, i]) < 1e-14
+    adj_full = oracle.synth_adjoint(f, l)
+    adj_part = oracle.synth_adjoint(f, l, orders=[0, 3])
+    sel = np.isin(np.abs(ms), [0, 3])
+    np.testing.assert_allclose(adj_part[:, sel], adj_full[:, sel], atol=1e-13)
+    assert np.all(adj_part[:, ~sel] == 0)
+
+
+@pytest.mark.parametrize("kind", ["complex", "real"])
+def test_adjoint_is_gradient_of_squared_misfit(kind):
+    # The gradient of L(b) = sum |synth(b) - T|^2 with respect to the real and imaginary
+    # parts of every stored coefficient, packed as dL/dRe + i dL/dIm, equals
+    # 2 synth_adjoint(synth(b) - T); checked entry by entry with central differences
+    # (L is quadratic, so the differences are exact up to rounding).
+    l = 4
+    b = syn.coefficients(l, 1, seed=11, kind=kind)
+    T = syn.grid(l, 1, seed=12, kind=kind)
+
+    def loss(bb):
+        d = oracle.synth(bb, l, kind=kind) - T
+        return float(np.sum(np.abs(d) ** 2))
+
+    grad = 2.0 * oracle.synth_adjoint(oracle.synth(b, l, kind=kind) - T, l, kind=kind)[0]
+    h = 1e-5
+    for i in range(b.shape[1]):
+        for unit in (1.0, 1j):
+            bp = b.copy()
+            bm = b.copy()
+            bp[0, i] += h * unit
+            bm[0, i] -= h * unit
+            fd = (loss(bp) - loss(bm)) / (2 * h)
+            an = grad[i].real if unit == 1.0 else grad[i].imag
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (kind, i, unit, fd, an)
