@@ -2,8 +2,11 @@
 
 One step = synthesis of a batch of F fields (coefficients -> 2l x 4l grid) followed by
 analysis of that grid back to coefficients, on one MI355X, with every input already in
-device memory.  value = F * steps / (timed seconds).  The plan precompute is excluded and
-reported as t_plan_s.
+device memory.  value = F * steps / (timed seconds) for the split-FP32 butterfly (the
+--precision default); the plain FP64 butterfly and plain FP32 are timed the same way in the
+same run and reported under "variants", with the per-field relative l2 error of each
+variant against the FP64 butterfly on the full batch ("err_vs_fp64").  The plan precompute
+is excluded and reported as t_plan_s.
 
 The JSON line also carries
  * roofline: the stage with the largest share of the timed kernel time, its algorithmic
@@ -32,17 +35,23 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--per-field-steps", type=int, default=1,
+                    help="steps (each F single-field pairs) for the per-field FP64 variant")
     ap.add_argument("--l", type=int, default=1024)
     ap.add_argument("--fields", type=int, default=64)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split32", "fp32"])
+    ap.add_argument("--precision", default="split32", choices=["fp64", "split32", "fp32"])
+    ap.add_argument("--no-variants", action="store_true", help="time only --precision")
     ap.add_argument("--leaf-width", type=int, default=64)
     ap.add_argument("--eps", type=float, default=1e-12)
     ap.add_argument("--power", type=float, default=1.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-orders", type=int, default=12)
-    ap.add_argument("--cpu-fields", type=int, default=2)
+    ap.add_argument("--cpu-orders", type=int, default=24)
+    ap.add_argument("--cpu-fields", type=int, default=4,
+                    help="fields in the oracle sample (a multiple of 4 for the matrix-core variants)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 2 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -90,17 +99,19 @@ def cpu_baseline(plan, args, beta_np, grid_seed_np):
     t_leg = max(1e-9, (t1 - t0) + (t2 - t1) - t_fft_pair)
     t_full = (t_leg * w_all / w_s + t_fft_pair) * (F / Fs)
 
-    # GPU on the same sampled inputs (outside the timed region)
-    dev = torch.from_numpy(np.ascontiguousarray(beta_s)).to("cuda")
-    f_gpu = plan.synth(dev, precision=args.precision)
-    a_gpu = plan.analyze(torch.from_numpy(np.ascontiguousarray(grid_seed_np[:Fs])).to("cuda"),
-                         precision=args.precision)
-    torch.cuda.synchronize()
-    f_gpu = f_gpu.cpu().numpy()
-    a_gpu = a_gpu.cpu().numpy()[:, mask]
+    # GPU on the same sampled inputs (outside the timed region), every variant
+    dev_b = torch.from_numpy(np.ascontiguousarray(beta_s)).to("cuda")
+    dev_g = torch.from_numpy(np.ascontiguousarray(grid_seed_np[:Fs])).to("cuda")
     a_ref = a_ref[:, mask]
-    e_s = [float(np.linalg.norm(f_gpu[i] - f_ref[i]) / np.linalg.norm(f_ref[i])) for i in range(Fs)]
-    e_a = [float(np.linalg.norm(a_gpu[i] - a_ref[i]) / np.linalg.norm(a_ref[i])) for i in range(Fs)]
+    errs = {}
+    for prec in dict.fromkeys([args.precision, "fp64"]):
+        f_gpu = plan.synth(dev_b, precision=prec).cpu().numpy()
+        a_gpu = plan.analyze(dev_g, precision=prec).cpu().numpy()[:, mask]
+        errs[prec] = {
+            "synth": [float(np.linalg.norm(f_gpu[i] - f_ref[i]) / np.linalg.norm(f_ref[i])) for i in range(Fs)],
+            "analysis": [float(np.linalg.norm(a_gpu[i] - a_ref[i]) / np.linalg.norm(a_ref[i]))
+                         for i in range(Fs)],
+        }
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     return {
         "value": F / t_full,
@@ -109,9 +120,92 @@ def cpu_baseline(plan, args, beta_np, grid_seed_np):
         "kind": "oracle",
         "sample": f"{len(sample)} of {L2} orders ({sample[0]}..{sample[-1]}), {Fs} of {F} fields; "
                   f"measured {t3 - t0:.1f} s, extrapolated by degree counts to {t_full:.0f} s per batch",
-        "oracle_rel_err_synth": e_s,
-        "oracle_rel_err_analysis": e_a,
+        "gpu_rel_err_vs_oracle": errs,
     }
+
+
+def time_pairs(plan, prec, beta, grid, back, steps, warmup, profile=False):
+    """Warm up, then time `steps` synthesis+analysis pairs with events on the current stream.
+
+    Returns (total ms, per-step ms list, wall seconds, profile or None)."""
+    import torch
+
+    for _ in range(warmup):
+        plan.synth(beta, out=grid, precision=prec)
+        plan.analyze(grid, out=back, precision=prec)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile_reset()
+        plan.profile(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev[0].record()
+    for i in range(steps):
+        plan.synth(beta, out=grid, precision=prec)
+        plan.analyze(grid, out=back, precision=prec)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    prof = None
+    if profile:
+        plan.profile(False)
+        prof = plan.profile_read()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]), per, wall, prof
+
+
+def time_per_field(plan, beta, steps):
+    """Plain FP64 butterfly one field at a time (R = 4 columns: the vector kernels)."""
+    import torch
+
+    F = beta.shape[0]
+    g1 = torch.empty((1,) + plan.grid_shape, dtype=torch.complex128, device="cuda")
+    b1 = torch.empty((1, beta.shape[1]), dtype=torch.complex128, device="cuda")
+    fields = [beta[f:f + 1] for f in range(F)]
+    plan.synth(fields[0], out=g1, precision="fp64")
+    plan.analyze(g1, out=b1, precision="fp64")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        for f in range(F):
+            plan.synth(fields[f], out=g1, precision="fp64")
+            plan.analyze(g1, out=b1, precision="fp64")
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def stage_totals(prof, steps):
+    """Per butterfly step: the size-class launches ("level2.c0", "level2.c1") summed."""
+    import re
+
+    out = {}
+    for k, v in prof.items():
+        key = re.sub(r"\.c\d+/", "/", k)
+        out[key] = out.get(key, 0.0) + v["ms"] / steps
+    return dict(sorted(out.items()))
+
+
+def roofline(prof, ms_total, precision):
+    """The single kernel launch with the largest share of the timed kernel time."""
+    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    mean_s = rec["ms"] / rec["launches"] / 1e3
+    flops_rate = rec["flops"] / mean_s
+    bytes_rate = rec["bytes"] / mean_s
+    peak_f = PEAK["fp64"] if precision == "fp64" else PEAK["fp32"]
+    if rec["flops"] > 0 and rec["flops"] / max(rec["bytes"], 1.0) > peak_f / PEAK["hbm"]:
+        roof = {"bound": "mfma", "achieved": flops_rate / 1e12, "peak": peak_f / 1e12,
+                "unit": "TFLOP/s", "frac": flops_rate / peak_f}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_rate / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": bytes_rate / PEAK["hbm"]}
+    roof.update({"kernel": name, "mean_launch_ms": mean_s * 1e3, "launches": rec["launches"],
+                 "flops_per_launch": rec["flops"], "bytes_per_launch": rec["bytes"], "traffic": None,
+                 "share_of_step": rec["ms"] / ms_total})
+    return roof
 
 
 def main():
@@ -128,6 +222,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     l, F = args.l, args.fields
+    if args.calibrate_copy:
+        # plain copy of known size: 2 GiB read + 2 GiB written per launch
+        a = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.perf_counter()
     plan = Plan(l, eps=args.eps, leaf_width=args.leaf_width, precision=args.precision)
     t_plan = time.perf_counter() - t0
@@ -139,46 +241,45 @@ def main():
     beta = torch.from_numpy(beta_np).to("cuda")
     grid = torch.empty((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
     back = torch.empty_like(beta)
-    for _ in range(args.warmup):
-        plan.synth(beta, out=grid)
-        plan.analyze(grid, out=back)
-    torch.cuda.synchronize()
-    err_rt = rel_err_per_field(back, beta)
 
-    plan.profile_reset()
-    plan.profile(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    w0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.synth(beta, out=grid)
-        plan.analyze(grid, out=back)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    plan.profile(False)
-    ms_total = e0.elapsed_time(e1)
+    ms_total, per_step, wall, prof = time_pairs(plan, args.precision, beta, grid, back, args.steps,
+                                                args.warmup, profile=True)
     ms_step = ms_total / args.steps
     value = F * args.steps / (ms_total / 1e3)
-    prof = plan.profile_read()
+    err_rt = rel_err_per_field(back, beta)
+    print(f"# {args.precision}: {value:.1f} pairs/s, {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # dominant stage
-    name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    mean_s = rec["ms"] / rec["launches"] / 1e3
-    flops_rate = rec["flops"] / mean_s
-    bytes_rate = rec["bytes"] / mean_s
-    peak_f = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
-    if rec["flops"] > 0 and rec["flops"] / max(rec["bytes"], 1.0) > peak_f / PEAK["hbm"]:
-        roof = {"bound": "alu", "achieved": flops_rate / 1e12, "peak": peak_f / 1e12,
-                "unit": "TFLOP/s", "frac": flops_rate / peak_f}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_rate / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": bytes_rate / PEAK["hbm"]}
-    roof.update({"kernel": name, "mean_launch_ms": mean_s * 1e3, "launches": rec["launches"],
-                 "flops_per_launch": rec["flops"], "bytes_per_launch": rec["bytes"], "traffic": None,
-                 "share_of_step": rec["ms"] / ms_total})
+    variants = {}
+    if not args.no_variants:
+        for prec in ("fp64", "split32", "fp32"):
+            if prec == args.precision:
+                continue
+            ms_v, per_v, _, _ = time_pairs(plan, prec, beta, grid, back, args.steps, args.warmup)
+            variants[prec] = {"value": F * args.steps / (ms_v / 1e3), "ms_per_step": ms_v / args.steps,
+                              "ms_per_step_median": float(np.median(per_v))}
+            print(f"# {prec}: {variants[prec]['value']:.1f} pairs/s", file=sys.stderr, flush=True)
+        if args.per_field_steps > 0:
+            ms_pf = time_per_field(plan, beta, args.per_field_steps)
+            variants["fp64_per_field"] = {"value": F * args.per_field_steps / (ms_pf / 1e3),
+                                          "ms_per_step": ms_pf / args.per_field_steps,
+                                          "note": f"{F} single-field calls per direction per step"}
+            print(f"# fp64 per field: {variants['fp64_per_field']['value']:.1f} pairs/s", file=sys.stderr,
+                  flush=True)
+
+    # per-field error of each precision against the FP64 butterfly on the full batch: synthesis
+    # of the bench coefficients, and analysis of the FP64 grid
+    err64 = {}
+    g64 = plan.synth(beta, precision="fp64")
+    b64 = plan.analyze(g64, precision="fp64")
+    for prec in ([args.precision] if args.no_variants else ["split32", "fp32"]):
+        if prec == "fp64":
+            continue
+        es = rel_err_per_field(plan.synth(beta, out=grid, precision=prec), g64)
+        ea = rel_err_per_field(plan.analyze(g64, out=back, precision=prec), b64)
+        err64[prec] = {"synth_max": float(es.max()), "synth_median": float(np.median(es)),
+                       "analysis_max": float(ea.max()), "analysis_median": float(np.median(ea))}
+    del g64, b64
+    torch.cuda.synchronize()
 
     out = {
         "metric": METRIC,
@@ -188,6 +289,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(np.median(per_step)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -197,13 +299,16 @@ def main():
                                f"fields, grid {2 * l}x{4 * l}, coefficients CN(0,1)/(1+k)^{args.power}",
                    "l": l, "fields": F, "precision": args.precision, "leaf_width": args.leaf_width,
                    "eps": args.eps},
-        "roofline": roof,
+        "roofline": roofline(prof, ms_total, args.precision),
+        "variants": variants,
+        "err_vs_fp64": err64,
         "round_trip_rel_err_max": float(np.max(err_rt)),
         "t_plan_s": t_plan,
         "plan": {k: st[k] for k in ("k_max", "k_avg", "k_sd", "factor_entries", "dense_entries",
                                     "m_max_words", "device_bytes")},
         "wall_s_timed": wall,
-        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},
+        "stages_ms_per_step": stage_totals(prof, args.steps),
+        "launches_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},
     }
     if not args.no_cpu_baseline:
         grid_seed = syn.grid(l, min(args.cpu_fields, F), seed=1)

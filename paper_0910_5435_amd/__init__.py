@@ -4,6 +4,6 @@ The compute path lives in ``libsht.so`` (HIP kernels for gfx950 behind a C ABI);
 this package only binds it.  Importing the package does not load the library;
 the first call that needs it does, and raises ImportError if it was not built.
 """
-from .sht import Butterfly, Plan, coeff_index, gl_nodes, num_coeffs
+from .sht import Batch, Butterfly, Plan, coeff_index, gl_nodes, num_coeffs
 
-__all__ = ["Plan", "Butterfly", "coeff_index", "gl_nodes", "num_coeffs"]
+__all__ = ["Plan", "Batch", "Butterfly", "coeff_index", "gl_nodes", "num_coeffs"]

@@ -19,6 +19,10 @@ SHT_FP32 = 2
 SHT_COMPLEX = 0
 SHT_REAL = 1
 
+SHT_BATCH_SYNTH = 0
+SHT_BATCH_ANALYZE = 1
+SHT_BATCH_ADJOINT = 2
+
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [
@@ -50,6 +54,37 @@ class Stats(ctypes.Structure):
     ]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("plan", ctypes.c_void_p),
+        ("nfields", ctypes.c_int),
+        ("input", ctypes.c_void_p),
+        ("output", ctypes.c_void_p),
+    ]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("column_tile", ctypes.c_int),
+        ("wg_per_cu", ctypes.c_int),
+        ("queues", ctypes.c_int),
+        ("ms", ctypes.c_double),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("groups", ctypes.c_int),
+        ("launches", ctypes.c_int),
+        ("phases", ctypes.c_int),
+        ("items", ctypes.c_longlong),
+        ("columns", ctypes.c_longlong),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("config", BatchConfig),
+        ("grid", ctypes.c_int),
+    ]
+
+
 class ShtError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
@@ -78,6 +113,13 @@ SIGNATURES = {
     "sht_analyze_ex": (_I, [_P, _I, _P, _P, _I, _P, _S, _P]),
     "sht_synth_adjoint_ex": (_I, [_P, _I, _P, _P, _I, _P, _S, _P]),
     "sht_plan_stats": (_I, [_P, ctypes.POINTER(Stats)]),
+    "sht_batch_create": (_I, [ctypes.POINTER(Request), _I, _I, _I, _S, _P, ctypes.POINTER(_P)]),
+    "sht_batch_configure": (_I, [_P, ctypes.POINTER(BatchConfig)]),
+    "sht_batch_tune": (_I, [_P, _I, _P, ctypes.POINTER(BatchConfig)]),
+    "sht_batch_run": (_I, [_P, _P]),
+    "sht_batch_check": (_I, [_P, _P]),
+    "sht_batch_get_info": (_I, [_P, ctypes.POINTER(BatchInfo)]),
+    "sht_batch_destroy": (None, [_P]),
     "sht_coeff_index": (_LL, [_I, _I, _I, _I]),
     "sht_num_coeffs": (_LL, [_I, _I]),
     "sht_gl_nodes": (_I, [_I, _DP, _DP]),

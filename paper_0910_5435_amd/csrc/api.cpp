@@ -145,6 +145,9 @@ Work level_work(const sht_plan_s* P, int t, int R) {
 Work final_work(const sht_plan_s* P, int R) {
   return {2.0 * P->final_fac * R, 8.0 * (P->final_fac + (P->final_rows_v + P->final_rows_y) * R)};
 }
+Work class_work(const LaunchClass& c, int R) {
+  return {2.0 * c.fac * R, 8.0 * (c.fac + (c.rows_in + c.rows_out) * R)};
+}
 Work fft_work(const sht_plan_s* P, int F, int R) {
   const double N = 4.0 * P->l;
   const double rows = 2.0 * P->l * F;
@@ -179,7 +182,10 @@ int stage(sht_plan_s* P, hipStream_t s, const std::string& name, Work w, Fn&& la
     if (_rc != SHT_OK) return _rc;                       \
   } while (0)
 
-std::string fsuffix(int F) { return "/F" + std::to_string(F); }
+std::string fsuffix(int F, int precision) {
+  const char* tag = precision == SHT_SPLIT32 ? "/split32" : precision == SHT_FP32 ? "/fp32" : "/fp64";
+  return "/F" + std::to_string(F) + tag;
+}
 
 int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, int F, void* ws,
               size_t wsb, void* stream) {
@@ -191,11 +197,16 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
-  const std::string fs = fsuffix(F);
-  if (mfma_ok(R)) {  // the leaf kernels gather straight from the coefficient layout
-    Work wk = level_work(P, 0, R);  // its input rows are the coefficients themselves
-    STAGE("synth.level0" + fs, wk,
-          launch_level(P, 0, false, nullptr, w.v0, R, precision, s, const_cast<double*>(coeff)));
+  const std::string fs = fsuffix(F, precision);
+  // matrix-core path: one stage per size-class launch ("synth.level2.c1/F64/fp64"), so that every
+  // timed stage is exactly one kernel dispatch; the leaf kernels gather straight from the
+  // coefficient layout
+  const bool mf = mfma_ok(R);
+  if (mf) {
+    for (size_t c = 0; c < P->step_classes[0].size(); ++c)
+      STAGE("synth.level0.c" + std::to_string(c) + fs, class_work(P->step_classes[0][c], R),
+            launch_level(P, 0, false, nullptr, w.v0, R, precision, s, const_cast<double*>(coeff),
+                         static_cast<int>(c)));
   } else {
     STAGE("synth.layout" + fs, layout_work(P, F, R), launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
     STAGE("synth.level0" + fs, level_work(P, 0, R),
@@ -204,11 +215,25 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   for (int t = 1; t <= P->Lmax; ++t) {
     const double* in = (t - 1) % 2 ? w.v1 : w.v0;
     double* out = t % 2 ? w.v1 : w.v0;
-    STAGE("synth.level" + std::to_string(t) + fs, level_work(P, t, R),
-          launch_level(P, t, false, in, out, R, precision, s));
+    if (mf) {
+      for (size_t c = 0; c < P->step_classes[t].size(); ++c)
+        STAGE("synth.level" + std::to_string(t) + ".c" + std::to_string(c) + fs,
+              class_work(P->step_classes[t][c], R),
+              launch_level(P, t, false, in, out, R, precision, s, nullptr, static_cast<int>(c)));
+    } else {
+      STAGE("synth.level" + std::to_string(t) + fs, level_work(P, t, R),
+            launch_level(P, t, false, in, out, R, precision, s));
+    }
   }
-  STAGE("synth.final" + fs, final_work(P, R),
-        launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s));
+  if (mf) {
+    for (size_t c = 0; c < P->final_classes.size(); ++c)
+      STAGE("synth.final.c" + std::to_string(c) + fs, class_work(P->final_classes[c], R),
+            launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s,
+                         static_cast<int>(c)));
+  } else {
+    STAGE("synth.final" + fs, final_work(P, R),
+          launch_final(P, false, w.v0, w.v1, nullptr, nullptr, w.y, nullptr, R, precision, false, s));
+  }
   STAGE("synth.fft" + fs, fft_work(P, F, R), launch_fft_synth(P, w.y, grid, F, R, s));
   return SHT_OK;
 }
@@ -225,20 +250,29 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);
   const std::string pre = adjoint ? "adjoint." : "analysis.";
-  const std::string fs = fsuffix(F);
+  const std::string fs = fsuffix(F, precision);
   STAGE(pre + "fft" + fs, fft_work(P, F, R),
         launch_fft_analyze(P, grid, w.y, F, R, scale, adjoint ? 2.0 : 1.0, s));
   STAGE(pre + "final" + fs, final_work(P, R),
         launch_final(P, true, nullptr, nullptr, w.v0, w.v1, nullptr, w.y, R, precision, adjoint, s));
+  const bool mf = mfma_ok(R);
   for (int t = P->Lmax; t >= 1; --t) {
     const double* in = t % 2 ? w.v1 : w.v0;
     double* out = (t - 1) % 2 ? w.v1 : w.v0;
-    STAGE(pre + "level" + std::to_string(t) + fs, level_work(P, t, R),
-          launch_level(P, t, true, in, out, R, precision, s));
+    if (mf) {
+      for (size_t c = 0; c < P->step_classes[t].size(); ++c)
+        STAGE(pre + "level" + std::to_string(t) + ".c" + std::to_string(c) + fs,
+              class_work(P->step_classes[t][c], R),
+              launch_level(P, t, true, in, out, R, precision, s, nullptr, static_cast<int>(c)));
+    } else {
+      STAGE(pre + "level" + std::to_string(t) + fs, level_work(P, t, R),
+            launch_level(P, t, true, in, out, R, precision, s));
+    }
   }
-  if (mfma_ok(R)) {  // the transposed leaf kernels scatter straight into the coefficient layout
-    STAGE(pre + "level0" + fs, level_work(P, 0, R),
-          launch_level(P, 0, true, w.v0, nullptr, R, precision, s, coeff));
+  if (mf) {  // the transposed leaf kernels scatter straight into the coefficient layout
+    for (size_t c = 0; c < P->step_classes[0].size(); ++c)
+      STAGE(pre + "level0.c" + std::to_string(c) + fs, class_work(P->step_classes[0][c], R),
+            launch_level(P, 0, true, w.v0, nullptr, R, precision, s, coeff, static_cast<int>(c)));
   } else {
     STAGE(pre + "level0" + fs, level_work(P, 0, R),
           launch_level(P, 0, true, w.v0, w.xin, R, precision, s));

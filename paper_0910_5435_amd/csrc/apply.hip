@@ -298,9 +298,8 @@ hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* c
 }
 
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in, double* out,
-                        int R, int precision, hipStream_t s, double* coeff) {
-  (void)precision;
-  if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, precision, s, coeff);
+                        int R, int precision, hipStream_t s, double* coeff, int cls) {
+  if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, precision, s, coeff, cls);
   if (precision != SHT_FP64) return hipErrorNotSupported;
   const long long cnt = P->step_cnt[step];
   if (cnt == 0) return hipSuccess;
@@ -331,12 +330,11 @@ hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const dou
 
 hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R,
-                        int precision, bool adjoint, hipStream_t s) {
-  (void)precision;
+                        int precision, bool adjoint, hipStream_t s, int cls) {
   if (P->n_final == 0) return hipSuccess;
   // the transposed MFMA kernel keeps at most 24 row tiles (k0 + k1 <= 384) in registers
   if (mfma_ok(R) && (!transpose || P->final_maxk <= 192))
-    return launch_final_mfma(P, transpose, v0, v1, v0w, v1w, y, yin, R, precision, adjoint, s);
+    return launch_final_mfma(P, transpose, v0, v1, v0w, v1w, y, yin, R, precision, adjoint, s, cls);
   if (precision != SHT_FP64) return hipErrorNotSupported;
   const int RT = pick_rt(R, std::max(2LL * P->final_maxk, 64LL * 2));
   dim3 grid(static_cast<unsigned>(P->n_final), R / RT);

@@ -3,15 +3,14 @@
 //
 //  * FP64: v_mfma_f64_16x16x4f64.
 //  * split: every FP64 operand x is cut into x1 + x2 where x1 keeps the top bits on a grid
-//    common to its row (factors) or column (vectors), |x1| <= 2^10 grid units, and x2 =
-//    fp32(x - x1).  The product sum a1 b1 is exact in FP32 as long as at most 16 products
-//    are chained (2^20 per product, 2^24 per FP32 significand), so it runs on
-//    v_mfma_f32_16x16x4f32 without rounding and is added into an FP64 accumulator every
-//    four K-steps; the three correction products a1 b2 + a2 b1 + a2 b2 (2^-10 of the
-//    result and smaller) are accumulated in FP32 for one K-step and then added into the
-//    FP64 accumulator, which keeps their rounding near 2^-34 of the result.  Factor slices
-//    are prepared once per plan; vector slices are cut on the fly from per-task, per-column
-//    scales.
+//    common to its row (factors) or column (vectors), |x1| <= 2^11 grid units, and x2 =
+//    fp32(x - x1).  One K-step sums four products a1 b1 of at most 2^22 grid units each,
+//    which FP32 holds exactly (2^24), so it runs on v_mfma_f32_16x16x4f32 without rounding
+//    and is added into an FP64 accumulator after every K-step; the correction products
+//    a2 b2 + a2 b1 + a1 b2 (about 2^-22 and 2^-11 of the result, chained smallest first)
+//    are summed in FP32 for one K-step and then added into the FP64 accumulator as well,
+//    which keeps their rounding near 2^-35 of the result.  Factor slices are prepared once
+//    per plan; vector slices are cut on the fly from per-task, per-column scales.
 //  * FP32: plain v_mfma_f32_16x16x4f32 on fp32(a), fp32(b), FP32 accumulation.
 //
 // Each interpolation is a small GEMM with a gathered operand: out = in[skel] + T in[red]
@@ -38,7 +37,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcd = 8;
-constexpr int kSliceBits = 10;  // |x1| <= 2^10 units of the row / column grid
+constexpr int kSliceBits = 11;  // |x1| <= 2^11 units of the row / column grid
 
 enum { P64 = 0, PSPLIT = 1, P32 = 2 };
 
@@ -54,11 +53,6 @@ template <int PREC>
 __device__ __forceinline__ int drow(int v, int lr) { return PREC == P64 ? 4 * v + lr : 4 * lr + v; }
 
 // ---------------------------------------------------------------- operands and accumulators
-struct FacPtr {
-  const double* d;  // FP64 entries
-  const float* hi;  // split: leading slice, row-aligned
-  const float* lo;  // split: fp32 remainder
-};
 
 template <int PREC> struct AFrag;
 template <> struct AFrag<P64> { double a; };
@@ -122,22 +116,18 @@ struct Acc<PSPLIT> {
   __device__ void set(int e, double x) { hi[e] = x; }
   __device__ void step(const AFrag<PSPLIT>& a, const BFrag<PSPLIT>& b) {
     ex = mfma32(a.a1, b.b1, ex);  // exact
-    cr = mfma32(a.a1, b.b2, cr);
+    cr = mfma32(a.a2, b.b2, cr);  // corrections, smallest first
     cr = mfma32(a.a2, b.b1, cr);
-    cr = mfma32(a.a2, b.b2, cr);
+    cr = mfma32(a.a1, b.b2, cr);
   }
-  // corrections: after every K-step
+  // after every K-step: the exact leading sum (at most four products) and the corrections
   __device__ void flush_step() {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(cr[e]);
-    cr = f4{0.f, 0.f, 0.f, 0.f};
-  }
-  // exact leading products: at most every four K-steps
-  __device__ void flush() {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(ex[e]);
+    for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(ex[e]) + static_cast<double>(cr[e]);
     ex = f4{0.f, 0.f, 0.f, 0.f};
+    cr = ex;
   }
+  __device__ void flush() {}
   __device__ double get(int e) const {
     return hi[e] + static_cast<double>(ex[e]) + static_cast<double>(cr[e]);
   }
@@ -196,30 +186,25 @@ inline unsigned xcd_grid(long long ntasks, int nblk) {
 template <int NT>
 constexpr int ldp() { return NT + 2; }
 
-// Where a leaf task's vector rows live when they are read from / written to the caller's
-// coefficient array directly (the layout change fused into the leaf level).
-struct CoefIO {
-  double* coeff;  // null: use the internal row buffer instead
-  const PairDesc* pairs;
-  long long ncoef;
-  int l, kind;
-};
-
-// Position in the coefficient array of row j, local column c of a leaf block (-1: no such
-// entry, -2: the imaginary part at m = 0 of a real field).
-__device__ __forceinline__ long long leaf_pos(const CoefIO& io, int m, int p, int j0, int j, long long col) {
+// Address of row j, local column col of a leaf block in the caller's coefficients; null if
+// there is no such entry (the -m half at m = 0, padding).  imag0: the imaginary part at
+// m = 0 of a real field, which reads as 0 and is written as 0.
+__device__ __forceinline__ double* leaf_ptr(const CoefIO& io, int m, int p, int j0, int j, long long col,
+                                            bool& imag0) {
   const int k = m + p + 2 * (j0 + j);
   const int cc = static_cast<int>(col & 1);
+  imag0 = false;
   if (io.kind == SHT_COMPLEX) {
     const int f = static_cast<int>(col >> 2), s = static_cast<int>((col >> 1) & 1);
-    return (m == 0 && s == 1) ? -1 : coeff_pos(io.l, SHT_COMPLEX, io.ncoef, f, m, s, k, cc);
+    return (m == 0 && s == 1) ? nullptr : io.at(f, m, s, k, cc);
   }
   const int f = static_cast<int>(col >> 1);
-  return (m == 0 && cc == 1) ? -2 : coeff_pos(io.l, SHT_REAL, io.ncoef, f, m, 0, k, cc);
+  imag0 = m == 0 && cc == 1;
+  return io.at(f, m, 0, k, cc);
 }
 
 // Visits the K x NT block of a leaf task in an order where consecutive threads touch
-// consecutive degrees of one (field, sign): fn(j, c, position).
+// consecutive degrees of one (field, sign): fn(j, c, address, imag0).
 template <int NT, typename Fn>
 __device__ __forceinline__ void for_leaf_block(const CoefIO& io, int m, int p, int j0, int K,
                                                long long c0, Fn&& fn) {
@@ -227,35 +212,35 @@ __device__ __forceinline__ void for_leaf_block(const CoefIO& io, int m, int p, i
     const int cc = e & 1;
     const int j = (e >> 1) % K;
     const int c = ((e >> 1) / K) * 2 + cc;
-    fn(j, c, leaf_pos(io, m, p, j0, j, c0 + c));
+    bool imag0;
+    double* a = leaf_ptr(io, m, p, j0, j, c0 + c, imag0);
+    fn(j, c, a, imag0);
   }
 }
 
 // ------------------------------------------------------------------- level, synthesis
+// One (task, column block): out_o = in[skel_o] + T_o in[red_o] for the task's outputs.  The
+// input block is staged in `lds` (K x (NT + 2) doubles, then the index lists).
 template <int NT, int PREC>
-__global__ void __launch_bounds__(256)
-k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
-                   const uint16_t* __restrict__ idx, const double* __restrict__ in,
-                   double* __restrict__ out, int R, CoefIO io) {
+__device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
+                                 const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                                 const double* __restrict__ in, double* __restrict__ out, int R,
+                                 const CoefIO& io, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  extern __shared__ double lds[];
   __shared__ double red_s[256];
   __shared__ int colsc[NT];
-  long long ti;
-  int blk;
-  if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  const LevelTask tk = tasks[ti];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
   double* xs = lds;                                          // K x LD
   uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * LD);  // [skel0 red0 skel1 red1]
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
-  if (io.coeff && tk.mp >= 0) {
-    const PairDesc pd = io.pairs[tk.mp];
-    const double* cf = io.coeff;
+  if (io.on() && tk.mp >= 0) {
+    const PairDesc pd = pairs[tk.mp];
     for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0,
-                       [&](int j, int c, long long pos) { xs[j * LD + c] = pos >= 0 ? cf[pos] : 0.0; });
+                       [&](int j, int c, const double* a, bool imag0) {
+                         xs[j * LD + c] = (a && !imag0) ? *a : 0.0;
+                       });
   } else {
     const double* src = in + static_cast<long long>(tk.in_row) * R + c0;
     for (int e = threadIdx.x; e < K * (NT / 2); e += 256) {
@@ -362,6 +347,18 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   }
 }
 
+template <int NT, int PREC>
+__global__ void __launch_bounds__(256)
+k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                   const double* __restrict__ in, double* __restrict__ out, int R, CoefIO io) {
+  extern __shared__ double lds[];
+  long long ti;
+  int blk;
+  if (!xcd_map(ntasks, nblk, ti, blk)) return;
+  level_synth_body<NT, PREC>(tasks[ti], blk, fp, idx, pairs, in, out, R, io, lds);
+}
+
 // ------------------------------------------------------------------ level, transposed
 // LDS holds the accumulated input block (K x NT) and the index lists; the vectors w_o of
 // the output blocks are read as B fragments straight from global memory (prefetched with
@@ -369,19 +366,14 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 // rows skel_o (assigned for o = 0, added for o = 1; every row gets exactly one term per
 // block).
 template <int NT, int PREC>
-__global__ void __launch_bounds__(256)
-k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
-                   const uint16_t* __restrict__ idx, const double* __restrict__ win,
-                   double* __restrict__ xout, int R, CoefIO io) {
+__device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
+                                 const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                                 const double* __restrict__ win, double* __restrict__ xout, int R,
+                                 const CoefIO& io, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  extern __shared__ double lds[];
   __shared__ double red_s[256];
   __shared__ int colsc[2][NT];
-  long long ti;
-  int blk;
-  if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  const LevelTask tk = tasks[ti];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
   const int nouts = tk.k[1] < 0 ? 1 : 2;
@@ -497,17 +489,12 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
     }
     __syncthreads();
   }
-  if (io.coeff && tk.mp >= 0) {
-    const PairDesc pd = io.pairs[tk.mp];
-    double* cf = io.coeff;
-    const int j0 = tk.in_row - pd.in_base;
-    for_leaf_block<NT>(io, pd.m, pd.p, j0, K, c0, [&](int j, int c, long long pos) {
-      if (pos >= 0)
-        cf[pos] = acc_l[j * LD + c];
-      else if (pos == -2)  // imaginary part at m = 0 of a real field
-        cf[coeff_pos(io.l, SHT_REAL, io.ncoef, static_cast<int>((c0 + c) >> 1), 0, 0,
-                     pd.p + 2 * (j0 + j), 1)] = 0.0;
-    });
+  if (io.on() && tk.mp >= 0) {
+    const PairDesc pd = pairs[tk.mp];
+    for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0,
+                       [&](int j, int c, double* a, bool imag0) {
+                         if (a) *a = imag0 ? 0.0 : acc_l[j * LD + c];
+                       });
     return;
   }
   double* xb = xout + static_cast<long long>(tk.in_row) * R + c0;
@@ -518,22 +505,29 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   }
 }
 
-// ------------------------------------------------------------------- final, synthesis
-// E = S_0 v_0, O = S_1 v_1 on one 16-row tile; g(+-x) = (E +- O) / D.
 template <int NT, int PREC>
 __global__ void __launch_bounds__(256)
-k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
-                   const double* __restrict__ v0buf, const double* __restrict__ v1buf,
-                   const double* __restrict__ invD, double* __restrict__ Y, int l, int R) {
-  constexpr int NTL = NT / 16;
-  constexpr int LD = ldp<NT>();
+k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                   const double* __restrict__ win, double* __restrict__ xout, int R, CoefIO io) {
   extern __shared__ double lds[];
-  __shared__ double red_s[256];
-  __shared__ int colsc[2][NT];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  const FinalTask ft = tasks[ti];
+  level_trans_body<NT, PREC>(tasks[ti], blk, fp, idx, pairs, win, xout, R, io, lds);
+}
+
+// ------------------------------------------------------------------- final, synthesis
+// E = S_0 v_0, O = S_1 v_1 on one 16-row tile; g(+-x) = (E +- O) / D.
+template <int NT, int PREC>
+__device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
+                                 const double* __restrict__ v0buf, const double* __restrict__ v1buf,
+                                 const double* __restrict__ invD, double* __restrict__ Y, int l, int R,
+                                 double* lds) {
+  constexpr int NTL = NT / 16;
+  constexpr int LD = ldp<NT>();
+  __shared__ double red_s[256];
+  __shared__ int colsc[2][NT];
   const long long c0 = static_cast<long long>(blk) * NT;
   const double* V = ft.vbuf ? v1buf : v0buf;
   const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
@@ -637,24 +631,36 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
   }
 }
 
-// ------------------------------------------------------------------ final, transposed
-// v_p = S_p^T (half * scale * (G(+x) +- G(-x))): the folded rows are built in LDS chunk by
-// chunk; each wave keeps the accumulators of its row tiles across the chunks.
-template <int NT, int ICH, int PREC>
+template <int NT, int PREC>
 __global__ void __launch_bounds__(256)
-k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
-                   const double* __restrict__ Yin, const double* __restrict__ scale, double half,
-                   double* __restrict__ v0buf, double* __restrict__ v1buf, int l, int R) {
-  constexpr int NTL = NT / 16;
-  constexpr int LD = ldp<NT>();
-  constexpr int MAXT = 6;  // row tiles per wave (k0 + k1 <= 384)
-  __shared__ double eo[2][ICH * LD];
-  __shared__ double red_s[256];
-  __shared__ int colsc[2][NT];
+k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const double* __restrict__ v0buf, const double* __restrict__ v1buf,
+                   const double* __restrict__ invD, double* __restrict__ Y, int l, int R) {
+  extern __shared__ double lds[];
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  const FinalTask ft = tasks[ti];
+  final_synth_body<NT, PREC>(tasks[ti], blk, fp, v0buf, v1buf, invD, Y, l, R, lds);
+}
+
+// ------------------------------------------------------------------ final, transposed
+// v_p = S_p^T (half * scale * (G(+x) +- G(-x))): the folded rows are built in LDS chunk by
+// chunk; each wave keeps the accumulators of its row tiles across the chunks.
+// LDS: the two folded chunks, 2 x ICH x (NT + 2) doubles.
+template <int NT, int ICH>
+constexpr size_t final_trans_lds() { return 2 * ICH * ldp<NT>() * sizeof(double); }
+
+template <int NT, int ICH, int PREC>
+__device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
+                                 const double* __restrict__ Yin, const double* __restrict__ scale,
+                                 double half, double* __restrict__ v0buf, double* __restrict__ v1buf,
+                                 int l, int R, double* lds) {
+  constexpr int NTL = NT / 16;
+  constexpr int LD = ldp<NT>();
+  constexpr int MAXT = 6;  // row tiles per wave (k0 + k1 <= 384)
+  double* eo[2] = {lds, lds + ICH * LD};
+  __shared__ double red_s[256];
+  __shared__ int colsc[2][NT];
   const long long c0 = static_cast<long long>(blk) * NT;
   double* V = ft.vbuf ? v1buf : v0buf;
   const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
@@ -745,6 +751,18 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
   }
 }
 
+template <int NT, int ICH, int PREC>
+__global__ void __launch_bounds__(256)
+k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                   const double* __restrict__ Yin, const double* __restrict__ scale, double half,
+                   double* __restrict__ v0buf, double* __restrict__ v1buf, int l, int R) {
+  extern __shared__ double lds[];
+  long long ti;
+  int blk;
+  if (!xcd_map(ntasks, nblk, ti, blk)) return;
+  final_trans_body<NT, ICH, PREC>(tasks[ti], blk, fp, Yin, scale, half, v0buf, v1buf, l, R, lds);
+}
+
 // ------------------------------------------------------------------ factor preparation
 __global__ void k_transpose_blocks(const double* __restrict__ fac, double* __restrict__ fac_t,
                                    const FactorBlock* __restrict__ blocks) {
@@ -808,7 +826,8 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
 #define LEVEL_LAUNCH(KER)                                                                              \
   do {                                                                                                 \
     if ((e = allow_lds(reinterpret_cast<const void*>(&KER), lds)) != hipSuccess) return e;             \
-    hipLaunchKernelGGL(KER, grid, dim3(256), lds, s, tasks, cnt, nblk, fp, P->d.idx, in, out, R, io);  \
+    hipLaunchKernelGGL(KER, grid, dim3(256), lds, s, tasks, cnt, nblk, fp, P->d.idx, P->d.pairs, in, out, \
+                       R, io);                                                                          \
   } while (0)
   if (!transpose) {
     if (NT == 32)
@@ -828,11 +847,13 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
 template <int PREC>
 hipError_t final_launch(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R, bool adjoint,
-                        hipStream_t s) {
+                        hipStream_t s, int only) {
   hipError_t e;
   const FacPtr fp = fac_ptr(P, transpose);
   if (!transpose) {
-    for (const LaunchClass& lc : P->final_classes) {
+    for (size_t c = 0; c < P->final_classes.size(); ++c) {
+      if (only >= 0 && static_cast<int>(c) != only) continue;
+      const LaunchClass& lc = P->final_classes[c];
       const long long cnt = lc.cnt;
       const FinalTask* tasks = P->d.finals + lc.off;
       const long long rows = 2LL * lc.maxk;
@@ -857,8 +878,115 @@ hipError_t final_launch(const sht_plan_s* P, bool transpose, const double* v0, c
   const int NT = 16;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
-  hipLaunchKernelGGL((k_final_trans_mfma<16, 128, PREC>), grid, dim3(256), 0, s, P->d.finals, cnt, nblk, fp, yin, scale, half, v0w, v1w, P->l, R);
+  const size_t lds_t = final_trans_lds<16, 128>();
+  hipLaunchKernelGGL((k_final_trans_mfma<16, 128, PREC>), grid, dim3(256), lds_t, s,
+                     P->d.finals, cnt, nblk, fp, yin, scale, half, v0w, v1w, P->l, R);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched persistent launch
+// Grid-wide barrier for a launch whose work-groups are all resident: arrive with release,
+// wait with acquire (agent scope, which writes back / invalidates the L2 of every XCD as
+// needed), give up after spin_limit polls and raise *status.  Returns false when the
+// launch is to be abandoned.
+__device__ bool grid_barrier(unsigned* ctr, unsigned nwg, int* status, long long spin_limit) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    long long polls = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < nwg) {
+      if (++polls > spin_limit || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    if (!ok) __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_ok != 0;
+}
+
+template <int NT, int PREC, bool TRANS>
+__device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* lds) {
+  const int t = it.step;
+  if (!TRANS) {
+    if (it.kind == kItemLevel) {
+      const double* in = t == 0 ? nullptr : ((t - 1) % 2 ? g.v1 : g.v0);
+      double* out = t % 2 ? g.v1 : g.v0;
+      level_synth_body<NT, PREC>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io, lds);
+    } else {
+      final_synth_body<NT, PREC>(g.finals[it.task], it.blk, g.fp, g.v0, g.v1, g.rowscale, g.y, g.l, g.R, lds);
+    }
+  } else {
+    if (it.kind == kItemLevel) {
+      const double* in = t % 2 ? g.v1 : g.v0;
+      double* out = t == 0 ? nullptr : ((t - 1) % 2 ? g.v1 : g.v0);
+      level_trans_body<NT, PREC>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io, lds);
+    } else {  // transposed finals always take 16-column blocks
+      final_trans_body<16, 128, PREC>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0, g.v1,
+                                      g.l, g.R, lds);
+    }
+  }
+}
+
+// Every work-group walks the phases in order; within a phase it takes items from its own
+// queue (queue = work-group id mod nq: with nq = 8 the queue of its XCD, since work-groups are
+// dealt to the XCDs round-robin) and then from the others, one atomic increment per item.
+template <int NT, int PREC, bool TRANS>
+__global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
+  extern __shared__ double lds[];
+  __shared__ int s_item;
+  const int nq = bl.nq;
+  const int myq = static_cast<int>(blockIdx.x % nq);
+  unsigned* heads = bl.sync;
+  unsigned* bars = bl.sync + static_cast<long long>(bl.nphase) * nq;
+  for (int ph = 0; ph < bl.nphase; ++ph) {
+    for (int d = 0; d < nq; ++d) {
+      const int q = (myq + d) % nq;
+      const int beg = bl.qoff[ph * nq + q], end = bl.qoff[ph * nq + q + 1];
+      if (beg == end) continue;
+      for (;;) {
+        if (threadIdx.x == 0) s_item = beg + static_cast<int>(atomicAdd(&heads[ph * nq + q], 1u));
+        __syncthreads();
+        const int i = s_item;
+        __syncthreads();
+        if (i >= end) break;
+        const BatchItem it = bl.items[i];
+        run_item<NT, PREC, TRANS>(it, bl.groups[it.group], lds);
+        __syncthreads();
+      }
+    }
+    if (ph + 1 < bl.nphase && !grid_barrier(&bars[ph], gridDim.x, bl.status, bl.spin_limit)) return;
+  }
+}
+
+__global__ void k_fill_u32(unsigned* p, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) p[i] = 0u;
+}
+
+template <int NT, int PREC, bool TRANS>
+const void* batch_fn() {
+  return reinterpret_cast<const void*>(&k_batch<NT, PREC, TRANS>);
+}
+
+const void* batch_kernel(int nt, int precision, bool trans) {
+#define PICK(NT_, P_)                                                             \
+  return trans ? batch_fn<NT_, P_, true>() : batch_fn<NT_, P_, false>();
+  if (nt == 32) {
+    if (precision == SHT_SPLIT32) PICK(32, PSPLIT)
+    if (precision == SHT_FP32) PICK(32, P32)
+    PICK(32, P64)
+  }
+  if (precision == SHT_SPLIT32) PICK(16, PSPLIT)
+  if (precision == SHT_FP32) PICK(16, P32)
+  PICK(16, P64)
+#undef PICK
 }
 
 }  // namespace
@@ -910,10 +1038,12 @@ hipError_t split_factors(sht_plan_s* P, hipStream_t s) {
 bool mfma_ok(int R) { return R % 16 == 0; }
 
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, int precision, hipStream_t s, double* coeff) {
-  CoefIO io{coeff, P->d.pairs,
+                             double* out, int R, int precision, hipStream_t s, double* coeff, int only) {
+  CoefIO io{coeff, nullptr,
             P->kind == SHT_COMPLEX ? 4LL * P->l * P->l : 2LL * P->l * P->l + P->l, P->l, P->kind};
-  for (const LaunchClass& lc : P->step_classes[step]) {
+  for (size_t c = 0; c < P->step_classes[step].size(); ++c) {
+    if (only >= 0 && static_cast<int>(c) != only) continue;
+    const LaunchClass& lc = P->step_classes[step][c];
     hipError_t e;
     if (precision == SHT_SPLIT32)
       e = level_class<PSPLIT>(P, step, lc, transpose, in, out, R, io, s);
@@ -928,13 +1058,43 @@ hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, cons
 
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
-                             int precision, bool adjoint, hipStream_t s) {
+                             int precision, bool adjoint, hipStream_t s, int only) {
   if (P->n_final == 0) return hipSuccess;
   if (precision == SHT_SPLIT32)
-    return final_launch<PSPLIT>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
+    return final_launch<PSPLIT>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s, only);
   if (precision == SHT_FP32)
-    return final_launch<P32>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
-  return final_launch<P64>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s);
+    return final_launch<P32>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s, only);
+  return final_launch<P64>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s, only);
 }
+
+hipError_t batch_kernel_prepare(int nt, int precision, bool transpose, size_t lds, int* wg_per_cu) {
+  if (nt != 16 && nt != 32) return hipErrorInvalidValue;
+  const void* fn = batch_kernel(nt, precision, transpose);
+  hipError_t e = allow_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  int n = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, lds);
+  if (e != hipSuccess) return e;
+  *wg_per_cu = n;
+  return hipSuccess;
+}
+
+hipError_t launch_batch_kernel(int nt, int precision, bool transpose, const BatchLaunch& bl, unsigned grid,
+                               size_t lds, hipStream_t s) {
+  if (nt != 16 && nt != 32) return hipErrorInvalidValue;
+  const void* fn = batch_kernel(nt, precision, transpose);
+  BatchLaunch arg = bl;
+  void* args[] = {&arg};
+  return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, s);
+}
+
+hipError_t launch_fill_u32(unsigned* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+size_t final_trans_lds_bytes() { return final_trans_lds<16, 128>(); }
 
 }  // namespace sht

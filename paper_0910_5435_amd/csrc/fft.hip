@@ -9,6 +9,8 @@
 // scaled by 1/N (analysis) or 1 (adjoint).  A Y row holds all fields of one (m, ring),
 // so work-groups are numbered field-fastest within each XCD: the groups of one ring run
 // together on one XCD and share the L2 lines of their Y gathers and scatters.
+#include <atomic>
+
 #include "sht_internal.h"
 
 namespace sht {
@@ -81,9 +83,16 @@ __device__ __forceinline__ bool ring_field(int rings, int F, int& ring, int& f) 
   return true;
 }
 
+// Base of field f's grid: the f-th block of a contiguous [field][ring][phi] array, or the
+// f-th entry of a per-field pointer table.
+__device__ __forceinline__ double* field_grid(double* grid, double* const* fptr, int f, int l, int kind) {
+  if (fptr) return fptr[f];
+  return grid + static_cast<long long>(f) * (2LL * l) * (4LL * l) * (kind == SHT_COMPLEX ? 2 : 1);
+}
+
 __global__ void __launch_bounds__(kFftThreads)
-k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, const double* __restrict__ tw,
-            int l, int R, int F, int kind) {
+k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* const* __restrict__ fptr,
+            const double* __restrict__ tw, int l, int R, int F, int kind) {
   extern __shared__ double2 X[];
   const int L2 = 2 * l;
   int ring, f;
@@ -109,31 +118,33 @@ k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, const doubl
     X[bitrev(b, logN)] = v;
   }
   fft_lds(X, N, logN, tw, 1.0);
-  const long long rowbase = (static_cast<long long>(f) * L2 + ring) * N;
+  double* gb = field_grid(grid, fptr, f, l, kind);
+  const long long rowbase = static_cast<long long>(ring) * N;
   if (kind == SHT_COMPLEX) {
-    double2* out = reinterpret_cast<double2*>(grid) + rowbase;
+    double2* out = reinterpret_cast<double2*>(gb) + rowbase;
     for (int j = threadIdx.x; j < N; j += kFftThreads) out[j] = X[j];
   } else {
-    for (int j = threadIdx.x; j < N; j += kFftThreads) grid[rowbase + j] = X[j].x;
+    for (int j = threadIdx.x; j < N; j += kFftThreads) gb[rowbase + j] = X[j].x;
   }
 }
 
 __global__ void __launch_bounds__(kFftThreads)
-k_fft_analyze(const double* __restrict__ grid, double* __restrict__ Y, const double* __restrict__ tw,
-              int l, int R, int F, int kind, double scale, double real_pos) {
+k_fft_analyze(const double* __restrict__ grid, double* const* __restrict__ fptr, double* __restrict__ Y,
+              const double* __restrict__ tw, int l, int R, int F, int kind, double scale, double real_pos) {
   extern __shared__ double2 X[];
   const int L2 = 2 * l;
   int ring, f;
   if (!ring_field(L2, F, ring, f)) return;
   const int N = 4 * l;
   const int logN = 31 - __clz(N);
-  const long long rowbase = (static_cast<long long>(f) * L2 + ring) * N;
+  const double* gb = field_grid(const_cast<double*>(grid), fptr, f, l, kind);
+  const long long rowbase = static_cast<long long>(ring) * N;
   for (int j = threadIdx.x; j < N; j += kFftThreads) {
     double2 v;
     if (kind == SHT_COMPLEX)
-      v = reinterpret_cast<const double2*>(grid)[rowbase + j];
+      v = reinterpret_cast<const double2*>(gb)[rowbase + j];
     else
-      v = make_double2(grid[rowbase + j], 0.0);
+      v = make_double2(gb[rowbase + j], 0.0);
     X[bitrev(j, logN)] = v;
   }
   fft_lds(X, N, logN, tw, -1.0);
@@ -154,9 +165,21 @@ k_fft_analyze(const double* __restrict__ grid, double* __restrict__ Y, const dou
   }
 }
 
+// Raises a kernel's dynamic-LDS limit once per size (so that launches recorded into a graph
+// make no attribute calls after fft_prepare).
+std::atomic<size_t> g_lds_synth{65536}, g_lds_analyze{65536};
+
 hipError_t allow_lds_fft(const void* fn, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  std::atomic<size_t>& done = fn == reinterpret_cast<const void*>(&k_fft_synth) ? g_lds_synth : g_lds_analyze;
+  if (bytes <= done.load()) return hipSuccess;
+  const hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  if (e == hipSuccess) {
+    size_t cur = done.load();
+    while (cur < bytes && !done.compare_exchange_weak(cur, bytes)) {
+    }
+  }
+  return e;
 }
 
 unsigned fft_grid(int l, int F) {
@@ -166,23 +189,30 @@ unsigned fft_grid(int l, int F) {
 
 }  // namespace
 
+hipError_t fft_prepare(int l) {
+  const size_t bytes = sizeof(double2) * 4 * static_cast<size_t>(l);
+  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), bytes);
+  if (e == hipSuccess) e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), bytes);
+  return e;
+}
+
 hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
-                            hipStream_t s) {
+                            hipStream_t s, double* const* fptr) {
   const int N = 4 * P->l;
   hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), sizeof(double2) * N);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fft_synth, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
-                     y, grid, P->d.twiddle, P->l, R, F, P->kind);
+                     y, grid, fptr, P->d.twiddle, P->l, R, F, P->kind);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
-                              double scale, double real_pos, hipStream_t s) {
+                              double scale, double real_pos, hipStream_t s, double* const* fptr) {
   const int N = 4 * P->l;
   hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), sizeof(double2) * N);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fft_analyze, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
-                     grid, y, P->d.twiddle, P->l, R, F, P->kind, scale, real_pos);
+                     grid, fptr, y, P->d.twiddle, P->l, R, F, P->kind, scale, real_pos);
   return hipGetLastError();
 }
 

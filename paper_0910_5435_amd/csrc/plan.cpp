@@ -352,6 +352,9 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
       cls.back().cnt += 1;
       cls.back().maxK = std::max(cls.back().maxK, tk.K);
       cls.back().maxk = std::max(cls.back().maxk, kmx);
+      cls.back().fac += nf;
+      cls.back().rows_in += tk.K;
+      cls.back().rows_out += tk.k[0] + (tk.k[1] > 0 ? tk.k[1] : 0);
       tasks.push_back(tk);
       P->step_maxK[t] = std::max(P->step_maxK[t], tk.K);
       P->step_maxk[t] = std::max(P->step_maxk[t], kmx);
@@ -407,6 +410,9 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     P->final_classes.back().cnt += 1;
     P->final_classes.back().maxK = std::max(P->final_classes.back().maxK, ft.h);
     P->final_classes.back().maxk = std::max(P->final_classes.back().maxk, kmx);
+    P->final_classes.back().fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
+    P->final_classes.back().rows_in += ft.k[0] + ft.k[1];
+    P->final_classes.back().rows_out += 2.0 * ft.h;
     finals.push_back(ft);
     P->final_fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
     P->final_rows_v += ft.k[0] + ft.k[1];

@@ -111,6 +111,72 @@ struct LaunchClass {
   long long off, cnt;  // task range relative to the step's first task
   int maxK, maxk;      // largest input length and output rank in the range
   int cls;
+  // algorithmic work per R column: factor entries, vector rows read and written
+  double fac = 0.0, rows_in = 0.0, rows_out = 0.0;
+};
+
+// Factor entries in the orientation a transform reads: FP64, and the split copies.
+struct FacPtr {
+  const double* d;  // FP64 entries
+  const float* hi;  // split: leading slice, row-aligned
+  const float* lo;  // split: fp32 remainder
+};
+
+// Where a leaf task's vector rows live when they are read from / written to the caller's
+// coefficients directly (the layout change fused into the leaf level): one contiguous
+// [field][ncoef] array, or one base pointer per field (null entries: padding columns).
+struct CoefIO {
+  double* coeff;         // contiguous array, or null
+  double* const* fptr;   // per-field base pointers, or null
+  long long ncoef;
+  int l, kind;
+  __device__ bool on() const { return coeff != nullptr || fptr != nullptr; }
+  __device__ double* at(int f, int m, int s, int k, int c) const {
+    if (fptr) {
+      double* b = fptr[f];
+      return b ? b + coeff_pos(l, kind, 0, 0, m, s, k, c) : nullptr;
+    }
+    return coeff + coeff_pos(l, kind, ncoef, f, m, s, k, c);
+  }
+};
+
+// Batched execution: one group = one plan and a set of fields (R columns, padded), with its
+// own workspace; one item = one (task, column block) of one group.
+struct BatchGroupDev {
+  const LevelTask* tasks;
+  const FinalTask* finals;
+  FacPtr fp;                // orientation read by this direction
+  const uint16_t* idx;
+  const PairDesc* pairs;
+  const double* rowscale;   // synthesis: 1/D; analysis: D; adjoint: 1/D
+  double half;              // transposed final: 1/2 (analysis) or 1 (adjoint)
+  double* v0;
+  double* v1;
+  double* y;
+  CoefIO io;
+  int R, l;
+};
+enum { kItemLevel = 0, kItemFinal = 1 };
+struct BatchItem {
+  int32_t group;
+  int16_t kind;   // kItemLevel / kItemFinal
+  int16_t step;   // level step t
+  int32_t blk;    // column block
+  int32_t pad;
+  int64_t task;   // index into the plan's level tasks / finals
+};
+// Arguments of the persistent kernel: phases run in order with a grid-wide barrier between
+// them; the items of (phase, queue) are items[qoff[phase * nq + q] .. qoff[phase * nq + q + 1]);
+// sync holds one head counter per (phase, queue) then one barrier counter per phase, all zero
+// at launch; status is set to 1 if a barrier wait exceeds spin_limit polls.
+struct BatchLaunch {
+  const BatchGroupDev* groups;
+  const BatchItem* items;
+  const int* qoff;
+  int nphase, nq;
+  unsigned* sync;
+  int* status;
+  long long spin_limit;
 };
 
 }  // namespace sht
@@ -150,26 +216,39 @@ hipError_t launch_coeff_to_xin(const sht_plan_s* P, const double* coeff, double*
                                int R, hipStream_t s);
 hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* coeff, int F,
                                int R, hipStream_t s);
+// cls >= 0 (matrix-core path only): launch only that size class of the step / of the finals.
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in,
-                        double* out, int R, int precision, hipStream_t s, double* coeff = nullptr);
+                        double* out, int R, int precision, hipStream_t s, double* coeff = nullptr,
+                        int cls = -1);
 hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R,
-                        int precision, bool adjoint, hipStream_t s);
+                        int precision, bool adjoint, hipStream_t s, int cls = -1);
+// fptr (may be null): one grid base pointer per field instead of a contiguous array.
 hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
-                            hipStream_t s);
+                            hipStream_t s, double* const* fptr = nullptr);
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
-                              double scale, double real_pos, hipStream_t s);
+                              double scale, double real_pos, hipStream_t s,
+                              double* const* fptr = nullptr);
+hipError_t fft_prepare(int l);  // kernel attributes for 4l-point rows (before graph capture)
 hipError_t split_factors(sht_plan_s* P, hipStream_t s);
 bool mfma_ok(int R);
 // coeff (leaf step only, may be null): read the leaf input from (synthesis) or write the
 // leaf output to (transposed) the caller's coefficient array instead of the row buffer.
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
-                             double* out, int R, int precision, hipStream_t s, double* coeff);
+                             double* out, int R, int precision, hipStream_t s, double* coeff,
+                             int cls = -1);
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
-                             int precision, bool adjoint, hipStream_t s);
+                             int precision, bool adjoint, hipStream_t s, int cls = -1);
 hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock* blocks,
                              long long nblocks, hipStream_t s);
+// Persistent batched kernel (column tile nt = 16 or 32): sets the LDS attribute and returns
+// how many work-groups of it fit on one compute unit with `lds` bytes of dynamic LDS.
+hipError_t batch_kernel_prepare(int nt, int precision, bool transpose, size_t lds, int* wg_per_cu);
+hipError_t launch_batch_kernel(int nt, int precision, bool transpose, const BatchLaunch& bl,
+                               unsigned grid, size_t lds, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, long long n, hipStream_t s);
+size_t final_trans_lds_bytes();  // dynamic LDS of one transposed-final item
 
 // Legendre column generator (legendre_cols.hip): recurrence state for a batch of pairs.
 struct ColumnBatch {

@@ -1,0 +1,182 @@
+"""Batched execution: many requests with mixed bandlimits in one persistent launch replayed
+from a graph, checked against the oracle, against single transform calls, across replays,
+across tuner configurations and across workspace splits."""
+import numpy as np
+import pytest
+
+import oracle
+import sht_synthetic as syn
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_PLANS = {}
+
+
+def _plan(l, kind="complex", eps=1e-13):
+    from paper_0910_5435_amd import Plan
+
+    key = (l, kind, eps)
+    if key not in _PLANS:
+        _PLANS[key] = Plan(l, eps=eps, leaf_width=min(64, max(4, l // 2)), kind=kind)
+    return _PLANS[key]
+
+
+def _rel(a, b):
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def _requests(spec, op, seed=0):
+    """spec: list of (l, kind, nfields) -> [(plan, input, output)] with seeded inputs."""
+    reqs = []
+    for i, (l, kind, F) in enumerate(spec):
+        P = _plan(l, kind)
+        if op == "synth":
+            x = torch.from_numpy(syn.coefficients(l, F, seed=seed + i, kind=kind)).cuda()
+            dt = torch.complex128 if kind == "complex" else torch.float64
+            y = torch.full((F, 2 * l, 4 * l), float("nan"), dtype=dt, device="cuda")
+        else:
+            x = torch.from_numpy(syn.grid(l, F, seed=seed + i, kind=kind)).cuda()
+            y = torch.full((F, P.n_coeffs), complex("nan+nanj"), dtype=torch.complex128, device="cuda")
+        reqs.append((P, x, y))
+    return reqs
+
+
+def _oracle(op, l, kind, x):
+    if op == "synth":
+        return oracle.synth(x, l, kind=kind)
+    if op == "analyze":
+        return oracle.analyze(x, l, kind=kind)
+    return oracle.synth_adjoint(x, l, kind=kind)
+
+
+MIXED = [(16, "complex", 3), (32, "complex", 1), (8, "complex", 2), (32, "complex", 4),
+         (64, "complex", 5), (16, "real", 2), (64, "real", 1), (32, "real", 3)]
+
+
+@pytest.mark.parametrize("op", ["synth", "analyze", "adjoint"])
+def test_batch_mixed_bandlimits_match_oracle(op):
+    from paper_0910_5435_amd import Batch
+
+    reqs = _requests(MIXED, op, seed=40)
+    b = Batch(reqs, op=op, precision="fp64")
+    b.run()
+    b.check()
+    info = b.info()
+    print(f"batch {op}: {info}")
+    assert info["launches"] == 1
+    for (P, x, y) in reqs:
+        err = _rel(y.cpu().numpy(), _oracle(op, P.l, P.kind, x.cpu().numpy()))
+        assert err.max() < 1e-11, (op, P.l, P.kind, err)
+
+
+def test_batch_split_precision_matches_oracle():
+    from paper_0910_5435_amd import Batch
+
+    spec = [(32, "complex", 3), (64, "complex", 2), (64, "real", 3), (128, "complex", 1)]
+    for op in ("synth", "analyze"):
+        reqs = _requests(spec, op, seed=50)
+        b = Batch(reqs, op=op, precision="split32")
+        b.run()
+        b.check()
+        for (P, x, y) in reqs:
+            err = _rel(y.cpu().numpy(), _oracle(op, P.l, P.kind, x.cpu().numpy()))
+            print(f"batch split {op} l={P.l} {P.kind}: {err.max():.2e}")
+            assert err.max() < 1e-9
+
+
+def test_batch_equals_single_calls():
+    # the same kernels on the same columns: the batch must agree with one plan call per request
+    # (matrix-core path there: field counts that are multiples of 4) to the last bits
+    from paper_0910_5435_amd import Batch
+
+    spec = [(32, "complex", 4), (64, "complex", 8), (32, "complex", 4)]
+    reqs = _requests(spec, "synth", seed=60)
+    b = Batch(reqs, op="synth", precision="fp64")
+    b.run()
+    b.check()
+    worst = 0.0
+    for (P, x, y) in reqs:
+        ref = P.synth(x, precision="fp64")
+        d = (y - ref).abs().max().item() / ref.abs().max().item()
+        worst = max(worst, d)
+    print(f"batch vs single calls: max rel diff {worst:.3e}")
+    assert worst < 1e-14
+
+
+def test_batch_graph_replays_and_tuner_configurations_agree():
+    from paper_0910_5435_amd import Batch
+
+    spec = [(16, "complex", 2), (64, "complex", 3), (32, "real", 5)]
+    reqs = _requests(spec, "analyze", seed=70)
+    b = Batch(reqs, op="analyze", precision="fp64")
+    b.run()
+    b.check()
+    first = [y.clone() for (_, _, y) in reqs]
+    # replays, with eager work and synchronisation in between, each from poisoned outputs
+    for rep in range(3):
+        for (_, _, y) in reqs:
+            y.fill_(complex("nan+nanj"))
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        b.run()
+        b.check()
+        for (_, _, y), f in zip(reqs, first):
+            assert torch.equal(y, f), f"replay {rep} differs"
+        del junk
+    # every configuration the tuner may pick computes the same numbers
+    for tile in (16, 32):
+        for queues in (1, 8):
+            b.configure(column_tile=tile, wg_per_cu=1, queues=queues)
+            for (_, _, y) in reqs:
+                y.fill_(complex("nan+nanj"))
+            b.run()
+            b.check()
+            for (_, _, y), f in zip(reqs, first):
+                assert torch.equal(y, f), (tile, queues)
+    best = b.tune(reps=2)
+    print(f"tuned: {best}")
+    assert best["column_tile"] in (16, 32) and best["queues"] in (1, 8) and best["wg_per_cu"] >= 1
+    for (_, _, y) in reqs:
+        y.fill_(complex("nan+nanj"))
+    b.run()
+    b.check()
+    for (_, _, y), f in zip(reqs, first):
+        assert torch.equal(y, f)
+
+
+def test_batch_workspace_limit_splits_launches():
+    from paper_0910_5435_amd import Batch
+
+    spec = [(64, "complex", 8), (64, "complex", 8), (32, "complex", 8), (16, "complex", 4)]
+    reqs = _requests(spec, "synth", seed=80)
+    full = Batch(reqs, op="synth", precision="fp64")
+    ws_one = full.info()["workspace_bytes"]
+    full.close()
+    # half of what one launch needs: the l = 64 fields are cut into two 32-column groups that
+    # cannot share a launch, so the batch runs two launches that reuse one workspace
+    b = Batch(reqs, op="synth", precision="fp64", workspace_limit=ws_one // 2)
+    info = b.info()
+    print(f"split batch: {info}")
+    assert info["launches"] > 1 and info["workspace_bytes"] <= ws_one // 2
+    b.run()
+    b.check()
+    for (P, x, y) in reqs:
+        err = _rel(y.cpu().numpy(), oracle.synth(x.cpu().numpy(), P.l))
+        assert err.max() < 1e-11
+    # a limit below one 32-column chunk of the largest plan is refused
+    from paper_0910_5435_amd import _lib
+
+    with pytest.raises(_lib.ShtError) as ei:
+        Batch(reqs, op="synth", precision="fp64", workspace_limit=ws_one // 64)
+    assert ei.value.status == _lib.SHT_ENOMEM
