@@ -50,6 +50,12 @@ def parse():
     ap.add_argument("--cpu-orders", type=int, default=24)
     ap.add_argument("--cpu-fields", type=int, default=4,
                     help="fields in the oracle sample (a multiple of 4 for the matrix-core variants)")
+    ap.add_argument("--workload", default="metric", choices=["metric", "mixed"],
+                    help="metric: the l=1024, 64-field line; mixed: 96 requests of mixed bandlimits "
+                         "through the batched persistent launch, beside one call per request")
+    ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
+                    help="bandlimits of the mixed workload (uniform draw); the full set 64..2048 needs "
+                         "about 210 GB for its inputs and outputs alone")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 2 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -189,6 +195,24 @@ def stage_totals(prof, steps):
     return dict(sorted(out.items()))
 
 
+def measured_traffic(launch):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the kernel
+    source that is built now (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    ent = rec.get("launches", {}).get(launch)
+    src = os.path.join(ROOT, rec.get("kernel_source", ""))
+    if ent is None or not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return ent["bytes"]
+
+
 def roofline(prof, ms_total, precision):
     """The single kernel launch with the largest share of the timed kernel time."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
@@ -203,9 +227,94 @@ def roofline(prof, ms_total, precision):
         roof = {"bound": "hbm", "achieved": bytes_rate / 1e9, "peak": PEAK["hbm"] / 1e9,
                 "unit": "GB/s", "frac": bytes_rate / PEAK["hbm"]}
     roof.update({"kernel": name, "mean_launch_ms": mean_s * 1e3, "launches": rec["launches"],
-                 "flops_per_launch": rec["flops"], "bytes_per_launch": rec["bytes"], "traffic": None,
-                 "share_of_step": rec["ms"] / ms_total})
+                 "flops_per_launch": rec["flops"], "bytes_per_launch": rec["bytes"],
+                 "traffic": measured_traffic(name), "share_of_step": rec["ms"] / ms_total})
     return roof
+
+
+def mixed(args):
+    """96 requests, bandlimits uniform over a set, 1..16 complex fields each (default_rng(0));
+    one synthesis batch and one analysis batch (persistent launch, graph, tuned) per step,
+    against one synth + analyze call per request."""
+    import numpy as np
+    import torch
+
+    import sht_synthetic as syn
+    from paper_0910_5435_amd import Batch, Plan
+
+    bls = [int(v) for v in args.mixed_bandlimits.split(",")]
+    rng = np.random.default_rng(0)
+    ls = rng.choice(bls, 96)
+    fs = rng.integers(1, 17, 96)
+    t0 = time.perf_counter()
+    plans = {l: Plan(l, eps=args.eps, leaf_width=min(args.leaf_width, max(4, l // 2)))
+             for l in sorted(set(int(v) for v in ls))}
+    t_plan = time.perf_counter() - t0
+    print(f"# mixed: plans {sorted(plans)} in {t_plan:.1f} s", file=sys.stderr, flush=True)
+    reqs = []
+    for i, (l, F) in enumerate(zip(ls, fs)):
+        l, F = int(l), int(F)
+        P = plans[l]
+        c = torch.from_numpy(syn.coefficients(l, F, seed=i, power=args.power)).cuda()
+        g = torch.empty((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(c)
+        reqs.append((P, c, g, b))
+    fields = int(fs.sum())
+    out = {"metric": "mixed-request SHT synth+analysis pairs/s", "unit": "pairs/s",
+           "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "data": "synthetic",
+           "config": {"workload": f"96 requests, l uniform over {bls}, 1..16 complex fields each "
+                                  f"({fields} fields), coefficients CN(0,1)/(1+k)^{args.power}",
+                      "requests": 96, "fields": fields, "eps": args.eps},
+           "t_plan_s": t_plan}
+    for prec in ("split32", "fp64"):
+        bs = Batch([(P, c, g) for (P, c, g, _) in reqs], op="synth", precision=prec)
+        ba = Batch([(P, g, b) for (P, _, g, b) in reqs], op="analyze", precision=prec)
+        tuned = (bs.tune(reps=2), ba.tune(reps=2))
+        for _ in range(args.warmup):
+            bs.run()
+            ba.run()
+        bs.check()
+        ba.check()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            bs.run()
+            ba.run()
+        e1.record()
+        bs.check()
+        ba.check()
+        ms = e0.elapsed_time(e1) / args.steps
+        err = max(float(((b - c).abs().pow(2).sum(dim=1).sqrt() / c.abs().pow(2).sum(dim=1).sqrt()).max())
+                  for (_, c, _, b) in reqs)
+        # one synth + analyze call per request, same stream, same precision where it runs
+        # (split needs 4 | fields; those requests fall back to FP64 calls here)
+        for (P, c, g, b) in reqs:
+            p1 = prec if (c.shape[0] % 4 == 0 or prec == "fp64") else "fp64"
+            P.synth(c, out=g, precision=p1)
+            P.analyze(g, out=b, precision=p1)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            for (P, c, g, b) in reqs:
+                p1 = prec if (c.shape[0] % 4 == 0 or prec == "fp64") else "fp64"
+                P.synth(c, out=g, precision=p1)
+                P.analyze(g, out=b, precision=p1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_seq = e0.elapsed_time(e1) / args.steps
+        out[prec] = {"batched_pairs_per_s": fields / (ms / 1e3), "batched_ms_per_step": ms,
+                     "per_request_pairs_per_s": fields / (ms_seq / 1e3), "per_request_ms_per_step": ms_seq,
+                     "round_trip_rel_err_max": err, "tuned": {"synth": tuned[0], "analysis": tuned[1]},
+                     "batch_info": {"synth": bs.info(), "analysis": ba.info()}}
+        print(f"# mixed {prec}: batched {ms:.1f} ms/step, per request {ms_seq:.1f} ms/step, rt {err:.2e}",
+              file=sys.stderr, flush=True)
+        bs.close()
+        ba.close()
+    out["value"] = out["split32"]["batched_pairs_per_s"]
+    out["dtype"] = "f32"
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -214,6 +323,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "mixed":
+        return mixed(args)
     import numpy as np
     import torch
 

@@ -180,3 +180,43 @@ def test_batch_workspace_limit_splits_launches():
     with pytest.raises(_lib.ShtError) as ei:
         Batch(reqs, op="synth", precision="fp64", workspace_limit=ws_one // 64)
     assert ei.value.status == _lib.SHT_ENOMEM
+
+
+def _mixed_draw(bandlimits, n=96, seed=0):
+    """The mixed-request workload: n requests, bandlimit uniform over `bandlimits`, 1..16
+    fields each, drawn with default_rng(seed); coefficients seeded per request."""
+    rng = np.random.default_rng(seed)
+    ls = rng.choice(bandlimits, n)
+    fs = rng.integers(1, 17, n)
+    return [(int(l), "complex", int(f)) for l, f in zip(ls, fs)]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("split32", 1e-9)])
+def test_mixed_request_workload(precision, tol):
+    # 96 requests over six bandlimits (the workload's {64..2048} scaled by 1/8 so that the
+    # oracle can check every request), one persistent launch per direction, tuned
+    from paper_0910_5435_amd import Batch
+
+    spec = _mixed_draw([8, 16, 32, 64, 128, 256])
+    reqs = _requests(spec, "synth", seed=100)
+    b = Batch(reqs, op="synth", precision=precision)
+    cfg = b.tune(reps=1)
+    b.run()
+    b.check()
+    grids = [(P, y) for (P, _, y) in reqs]
+    back = [(P, y, torch.full((y.shape[0], P.n_coeffs), complex("nan+nanj"), dtype=torch.complex128,
+                              device="cuda")) for (P, y) in grids]
+    a = Batch(back, op="analyze", precision=precision)
+    a.run()
+    a.check()
+    info = b.info()
+    print(f"mixed {precision}: {info}, tuned {cfg}")
+    assert info["launches"] == 1
+    worst_s = worst_r = 0.0
+    for i, ((P, x, y), (_, _, z)) in enumerate(zip(reqs, back)):
+        xs = x.cpu().numpy()
+        ref = oracle.synth(xs[:1], P.l)  # first field of every request against the oracle
+        worst_s = max(worst_s, _rel(y.cpu().numpy()[:1], ref).max())
+        worst_r = max(worst_r, _rel(z.cpu().numpy(), xs).max())  # all fields: round trip
+    print(f"mixed {precision}: synth vs oracle {worst_s:.2e}, round trip {worst_r:.2e}")
+    assert worst_s < tol and worst_r < 2 * tol
