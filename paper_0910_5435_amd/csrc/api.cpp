@@ -209,8 +209,9 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
                          static_cast<int>(c)));
   } else {
     STAGE("synth.layout" + fs, layout_work(P, F, R), launch_coeff_to_xin(P, coeff, w.xin, F, R, s));
-    STAGE("synth.level0" + fs, level_work(P, 0, R),
-          launch_level(P, 0, false, w.xin, w.v0, R, precision, s));
+    if (P->step_cnt[0] > 0)
+      STAGE("synth.level0" + fs, level_work(P, 0, R),
+            launch_level(P, 0, false, w.xin, w.v0, R, precision, s, nullptr, -1, w.xin));
   }
   for (int t = 1; t <= P->Lmax; ++t) {
     const double* in = (t - 1) % 2 ? w.v1 : w.v0;
@@ -219,10 +220,11 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
       for (size_t c = 0; c < P->step_classes[t].size(); ++c)
         STAGE("synth.level" + std::to_string(t) + ".c" + std::to_string(c) + fs,
               class_work(P->step_classes[t][c], R),
-              launch_level(P, t, false, in, out, R, precision, s, nullptr, static_cast<int>(c)));
+              launch_level(P, t, false, in, out, R, precision, s, const_cast<double*>(coeff),
+                           static_cast<int>(c)));
     } else {
       STAGE("synth.level" + std::to_string(t) + fs, level_work(P, t, R),
-            launch_level(P, t, false, in, out, R, precision, s));
+            launch_level(P, t, false, in, out, R, precision, s, nullptr, -1, w.xin));
     }
   }
   if (mf) {
@@ -263,10 +265,10 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
       for (size_t c = 0; c < P->step_classes[t].size(); ++c)
         STAGE(pre + "level" + std::to_string(t) + ".c" + std::to_string(c) + fs,
               class_work(P->step_classes[t][c], R),
-              launch_level(P, t, true, in, out, R, precision, s, nullptr, static_cast<int>(c)));
+              launch_level(P, t, true, in, out, R, precision, s, coeff, static_cast<int>(c)));
     } else {
       STAGE(pre + "level" + std::to_string(t) + fs, level_work(P, t, R),
-            launch_level(P, t, true, in, out, R, precision, s));
+            launch_level(P, t, true, in, out, R, precision, s, nullptr, -1, w.xin));
     }
   }
   if (mf) {  // the transposed leaf kernels scatter straight into the coefficient layout
@@ -274,8 +276,9 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
       STAGE(pre + "level0.c" + std::to_string(c) + fs, class_work(P->step_classes[0][c], R),
             launch_level(P, 0, true, w.v0, nullptr, R, precision, s, coeff, static_cast<int>(c)));
   } else {
-    STAGE(pre + "level0" + fs, level_work(P, 0, R),
-          launch_level(P, 0, true, w.v0, w.xin, R, precision, s));
+    if (P->step_cnt[0] > 0)
+      STAGE(pre + "level0" + fs, level_work(P, 0, R),
+            launch_level(P, 0, true, w.v0, w.xin, R, precision, s, nullptr, -1, w.xin));
     STAGE(pre + "layout" + fs, layout_work(P, F, R), launch_xin_to_coeff(P, w.xin, coeff, F, R, s));
   }
   return SHT_OK;

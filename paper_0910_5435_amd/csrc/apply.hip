@@ -80,18 +80,21 @@ __global__ void k_xin_to_coeff(const PairDesc* __restrict__ pairs, const double*
 
 // ------------------------------------------------------------------------------- levels
 // Synthesis: out_o = in[skel_o] + T_o in[red_o] for the task's one or two outputs.
+// Tasks whose input rows are coefficients (mp >= 0: leaves, level-1 tasks over folded
+// leaves) read them from the internal coefficient rows `xin` instead of `in`.
 template <int RT>
 __global__ void __launch_bounds__(kThreads)
 k_level_synth(const LevelTask* __restrict__ tasks, const double* __restrict__ fac,
               const uint16_t* __restrict__ idx, const double* __restrict__ in,
-              double* __restrict__ out, int R) {
+              const double* __restrict__ xin, double* __restrict__ out, int R) {
   extern __shared__ double lds[];
   const LevelTask tk = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   const int K = tk.K;
+  const double* src = tk.mp >= 0 ? xin : in;
   for (int e = threadIdx.x; e < K * RT; e += kThreads) {
     const int row = e / RT, c = e % RT;
-    lds[e] = in[(static_cast<long long>(tk.in_row) + row) * R + r0 + c];
+    lds[e] = src[(static_cast<long long>(tk.in_row) + row) * R + r0 + c];
   }
   __syncthreads();
   for (int o = 0; o < 2; ++o) {
@@ -116,7 +119,7 @@ template <int RT>
 __global__ void __launch_bounds__(kThreads)
 k_level_trans(const LevelTask* __restrict__ tasks, const double* __restrict__ fac,
               const uint16_t* __restrict__ idx, const double* __restrict__ win,
-              double* __restrict__ xout, int R) {
+              double* __restrict__ xout, double* __restrict__ xin, int R) {
   extern __shared__ double lds[];
   const LevelTask tk = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
@@ -164,9 +167,10 @@ k_level_trans(const LevelTask* __restrict__ tasks, const double* __restrict__ fa
     }
     __syncthreads();
   }
+  double* dst = tk.mp >= 0 ? xin : xout;
   for (int e = threadIdx.x; e < K * RT; e += kThreads) {
     const int row = e / RT, c = e % RT;
-    xout[(static_cast<long long>(tk.in_row) + row) * R + r0 + c] = acc[e];
+    dst[(static_cast<long long>(tk.in_row) + row) * R + r0 + c] = acc[e];
   }
 }
 
@@ -298,7 +302,7 @@ hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* c
 }
 
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in, double* out,
-                        int R, int precision, hipStream_t s, double* coeff, int cls) {
+                        int R, int precision, hipStream_t s, double* coeff, int cls, double* xin) {
   if (mfma_ok(R)) return launch_level_mfma(P, step, transpose, in, out, R, precision, s, coeff, cls);
   if (precision != SHT_FP64) return hipErrorNotSupported;
   const long long cnt = P->step_cnt[step];
@@ -312,10 +316,10 @@ hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const dou
   do {                                                                                           \
     if (transpose)                                                                               \
       hipLaunchKernelGGL(k_level_trans<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac_t,    \
-                         P->d.idx, in, out, R);                                                  \
+                         P->d.idx, in, out, xin, R);                                             \
     else                                                                                         \
       hipLaunchKernelGGL(k_level_synth<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac,      \
-                         P->d.idx, in, out, R);                                                  \
+                         P->d.idx, in, xin, out, R);                                             \
   } while (0)
   switch (RT) {
     case 16: LAUNCH_LEVEL(16); break;

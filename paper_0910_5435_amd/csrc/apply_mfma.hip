@@ -26,6 +26,7 @@
 // i + 16k and B[k][j] in lane j + 16k; the FP64 result D[4v + lane/16][lane%16] is in
 // element v, the FP32 result D[4(lane/16) + v][lane%16].
 #include <algorithm>
+#include <cstdlib>
 
 #include "sht_internal.h"
 
@@ -798,6 +799,18 @@ __global__ void k_split_rows(const double* __restrict__ src, float* __restrict__
   }
 }
 
+// LDS budget (bytes) under which a level or final launch takes 32-column tiles instead of 16:
+// a larger tile halves the factor reads per task but its LDS block limits how many
+// work-groups share a compute unit.  SHT_TILE32_LDS_KB overrides it (tuning).
+long long tile32_lds_budget() {
+  static const long long v = [] {
+    const char* e = std::getenv("SHT_TILE32_LDS_KB");
+    const long long kb = e ? std::atoll(e) : 100;
+    return (kb > 0 ? kb : 100) * 1024;
+  }();
+  return v;
+}
+
 hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
@@ -816,7 +829,7 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
   // LDS holds the task's K x NT input block: 32 columns while that stays within 100 KiB
-  const int NT = (R % 32 == 0 && static_cast<long long>(K) * 34 * 8 <= 100 * 1024) ? 32 : 16;
+  const int NT = (R % 32 == 0 && static_cast<long long>(K) * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
   if (static_cast<long long>(K) * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
@@ -857,7 +870,7 @@ hipError_t final_launch(const sht_plan_s* P, bool transpose, const double* v0, c
       const long long cnt = lc.cnt;
       const FinalTask* tasks = P->d.finals + lc.off;
       const long long rows = 2LL * lc.maxk;
-      const int NT = (R % 32 == 0 && rows * 34 * 8 <= 80 * 1024) ? 32 : 16;
+      const int NT = (R % 32 == 0 && rows * 34 * 8 <= std::min(80LL * 1024, tile32_lds_budget())) ? 32 : 16;
       const int nblk = R / NT;
       const dim3 grid(xcd_grid(cnt, nblk));
       const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 16;

@@ -270,10 +270,11 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   P->step_fac.assign(Lmax + 1, 0.0);
   P->step_rows_in.assign(Lmax + 1, 0.0);
   P->step_rows_out.assign(Lmax + 1, 0.0);
-  auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off) {
+  // map (may be null): renumbering of the block's input indices (folded leaves, below)
+  auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off, const std::vector<int>* map) {
     idx_off = static_cast<int32_t>(idx.size());
-    for (int v : B.skel) idx.push_back(static_cast<uint16_t>(v));
-    for (int v : B.red) idx.push_back(static_cast<uint16_t>(v));
+    for (int v : B.skel) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
+    for (int v : B.red) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
     fac_off = static_cast<int64_t>(fac.size());
     fac.insert(fac.end(), B.T.begin(), B.T.end());
     if (!B.T.empty()) fblocks.push_back({fac_off, B.k, B.K - B.k});
@@ -285,7 +286,26 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   struct Proto {
     LevelTask tk;
     const BfBlock* b[2];
+    std::vector<int> map;  // folded leaves: level-1 input index -> leaf-pair column
   };
+  // Folded leaves.  The columns of Q^{(m,p)} are orthonormal, so every leaf block has full
+  // rank and its ID is a pure reordering (k = K, no T): w = x[skel].  For an order with at
+  // least one level above the leaves, the level-1 tasks read the coefficients of their two
+  // leaves directly (in column order) with their index lists renumbered through the
+  // leaves' skeleton orders, and the leaf step is dropped for that order.
+  std::vector<char> fold(npairs, 0);
+  for (int mp = 0; mp < npairs; ++mp) {
+    const BfTree& T = trees[mp];
+    if (T.L() < 1) continue;
+    bool ident = true;
+    for (int c = 0; c < T.ncol(0) && ident; ++c) {
+      const BfBlock& B = T.block(0, 0, c);
+      ident = B.k == B.K && B.red.empty();  // only the last non-empty leaf can be short
+    }
+    fold[mp] = ident;
+  }
+  P->n_folded = 0;
+  for (char f : fold) P->n_folded += f;
   P->step_classes.assign(Lmax + 1, {});
   for (int t = 0; t <= Lmax; ++t) {
     P->step_off[t] = static_cast<long long>(tasks.size());
@@ -295,6 +315,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
       if (T.L() < t) continue;
       const int vb = P->v_base[mp];
       if (t == 0) {
+        if (fold[mp]) continue;
         for (int c = 0; c < T.ncol(0); ++c) {
           const BfBlock& B = T.block(0, 0, c);
           if (B.K == 0) continue;
@@ -326,6 +347,15 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
             pr.tk.mp = -1;
             pr.b[0] = &Bt;
             pr.b[1] = &Bb;
+            if (t == 1 && fold[mp]) {
+              const BfBlock& Lf = T.block(0, 0, 2 * cc);
+              const int kl = Lf.k;
+              pr.tk.in_row = P->in_base[mp] + 2 * cc * T.C();
+              pr.tk.mp = mp;
+              pr.map.resize(Bt.K);
+              for (int v = 0; v < Bt.K; ++v)
+                pr.map[v] = v < kl ? Lf.skel[v] : Lf.K + T.block(0, 0, 2 * cc + 1).skel[v - kl];
+            }
             protos.push_back(pr);
           }
         }
@@ -337,11 +367,12 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     for (size_t i = 0; i < protos.size(); ++i) {
       Proto& pr = protos[i];
       LevelTask tk = pr.tk;
-      push_block(*pr.b[0], tk.idx[0], tk.fac[0]);
+      const std::vector<int>* map = pr.map.empty() ? nullptr : &pr.map;
+      push_block(*pr.b[0], tk.idx[0], tk.fac[0], map);
       int kmx = pr.b[0]->k;
       double nf = static_cast<double>(pr.b[0]->T.size());
       if (pr.b[1]) {
-        push_block(*pr.b[1], tk.idx[1], tk.fac[1]);
+        push_block(*pr.b[1], tk.idx[1], tk.fac[1], map);
         kmx = std::max(kmx, pr.b[1]->k);
         nf += static_cast<double>(pr.b[1]->T.size());
       }

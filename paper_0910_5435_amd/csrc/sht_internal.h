@@ -22,7 +22,8 @@ struct LevelTask {
   int32_t out_row[2]; // first row of each output block
   int32_t k[2];       // rank of each output block; k[1] = -1 for a leaf
   int32_t idx[2];     // offset of [skel (k) | red (K-k)] in the index pool
-  int32_t mp;         // leaf tasks: pair index 2m + p (their input comes from coefficients)
+  int32_t mp;         // pair index 2m + p if the input rows are coefficients (leaf tasks, and
+                      // level-1 tasks over folded identity leaves), else -1
   int64_t fac[2];     // offset of T (k x (K-k), column-major) in the factor pool
 };
 
@@ -205,6 +206,7 @@ struct sht_plan_s {
   sht::Profiler prof;
   long long n_final = 0;
   long long n_pairs = 0;
+  long long n_folded = 0;  // orders whose leaf step is folded into level 1
   sht::DeviceFactors d;
   sht_stats stats{};
 };
@@ -217,9 +219,11 @@ hipError_t launch_coeff_to_xin(const sht_plan_s* P, const double* coeff, double*
 hipError_t launch_xin_to_coeff(const sht_plan_s* P, const double* xin, double* coeff, int F,
                                int R, hipStream_t s);
 // cls >= 0 (matrix-core path only): launch only that size class of the step / of the finals.
+// Tasks whose input rows are coefficients (LevelTask::mp >= 0) read / write them through
+// `coeff` (matrix-core path: the caller's layout) or `xin` (vector path: internal rows).
 hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const double* in,
                         double* out, int R, int precision, hipStream_t s, double* coeff = nullptr,
-                        int cls = -1);
+                        int cls = -1, double* xin = nullptr);
 hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R,
                         int precision, bool adjoint, hipStream_t s, int cls = -1);
