@@ -16,7 +16,7 @@
 // Each interpolation is a small GEMM with a gathered operand: out = in[skel] + T in[red]
 // (synthesis) or in = sum_o scatter(T_o^T w_o, w_o) (transposed).  A work-group takes one
 // task and NT columns; every wave runs pairs of 16-row tiles with the factor fragments (A)
-// fetched four K-steps ahead from global memory (a stored column is contiguous, so 16 lanes
+// fetched kPrefetch K-steps ahead from global memory (a stored column is contiguous, so 16 lanes
 // read consecutive words) and the vector fragments (B) from LDS or global memory.
 // Work-groups are numbered so that all column blocks of one task land on the same XCD
 // (ids are dealt round-robin over the 8 XCDs): the factor block is read from HBM once and
@@ -39,6 +39,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kXcd = 8;
 constexpr int kSliceBits = 11;  // |x1| <= 2^11 units of the row / column grid
+constexpr int kPrefetch = 4;    // K-steps of factor fragments fetched ahead (double-buffered)
 
 enum { P64 = 0, PSPLIT = 1, P32 = 2 };
 
@@ -68,11 +69,13 @@ __device__ __forceinline__ AFrag<P64> load_a<P64>(const FacPtr& f, long long i, 
 }
 template <>
 __device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok) {
-  return {ok ? f.hi[i] : 0.0f, ok ? f.lo[i] : 0.0f};
+  const float2 v = ok ? f.hl[i] : make_float2(0.0f, 0.0f);
+  return {v.x, v.y};
 }
 template <>
 __device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok) {
-  return {ok ? f.hi[i] + f.lo[i] : 0.0f};
+  const float2 v = ok ? f.hl[i] : make_float2(0.0f, 0.0f);
+  return {v.x + v.y};
 }
 
 template <int PREC> struct BFrag;
@@ -115,13 +118,15 @@ struct Acc<PSPLIT> {
     cr = ex;
   }
   __device__ void set(int e, double x) { hi[e] = x; }
+  // one K-step from zero (every K-step is flushed): the exact leading sum of four products,
+  // then the corrections, smallest first
   __device__ void step(const AFrag<PSPLIT>& a, const BFrag<PSPLIT>& b) {
-    ex = mfma32(a.a1, b.b1, ex);  // exact
-    cr = mfma32(a.a2, b.b2, cr);  // corrections, smallest first
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    ex = mfma32(a.a1, b.b1, z);
+    cr = mfma32(a.a2, b.b2, z);
     cr = mfma32(a.a2, b.b1, cr);
     cr = mfma32(a.a1, b.b2, cr);
   }
-  // after every K-step: the exact leading sum (at most four products) and the corrections
   __device__ void flush_step() {
 #pragma unroll
     for (int e = 0; e < 4; ++e) hi[e] += static_cast<double>(ex[e]) + static_cast<double>(cr[e]);
@@ -219,6 +224,65 @@ __device__ __forceinline__ void for_leaf_block(const CoefIO& io, int m, int p, i
   }
 }
 
+// Staging loop with the global loads of kB items per thread issued before any of them is
+// used: v = load(e), then put(e, v), for e = threadIdx.x + 256 i < n.
+constexpr int kStage = 8;
+template <typename T, typename Load, typename Put>
+__device__ __forceinline__ void staged(int n, Load&& load, Put&& put) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += 256 * kStage) {
+    T v[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int e = e0 + u * 256;
+      if (e < n) v[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int e = e0 + u * 256;
+      if (e < n) put(e, v[u]);
+    }
+  }
+}
+
+// The K x NT block of a leaf task gathered from the coefficients into xs (row stride LD), in
+// the visiting order of for_leaf_block.
+template <int NT, int LD>
+__device__ __forceinline__ void gather_leaf_block(const CoefIO& io, int m, int p, int j0, int K,
+                                                  long long c0, double* xs) {
+  staged<double>(
+      K * NT,
+      [&](int e) {
+        const int cc = e & 1;
+        const int j = (e >> 1) % K;
+        const int c = ((e >> 1) / K) * 2 + cc;
+        bool imag0;
+        const double* a = leaf_ptr(io, m, p, j0, j, c0 + c, imag0);
+        return (a && !imag0) ? *a : 0.0;
+      },
+      [&](int e, double v) {
+        const int cc = e & 1;
+        const int j = (e >> 1) % K;
+        const int c = ((e >> 1) / K) * 2 + cc;
+        xs[j * LD + c] = v;
+      });
+}
+
+// rows x NT block of an R-wide row buffer (first row `src`) into LDS rows of stride LD.
+template <int NT, int LD>
+__device__ __forceinline__ void stage_rows(const double* __restrict__ src, int rows, int R, double* dst) {
+  staged<double2>(
+      rows * (NT / 2),
+      [&](int e) {
+        const int row = e / (NT / 2), c2 = e % (NT / 2);
+        return *reinterpret_cast<const double2*>(src + static_cast<long long>(row) * R + 2 * c2);
+      },
+      [&](int e, double2 v) {
+        const int row = e / (NT / 2), c2 = e % (NT / 2);
+        dst[row * LD + 2 * c2] = v.x;
+        dst[row * LD + 2 * c2 + 1] = v.y;
+      });
+}
+
 // ------------------------------------------------------------------- level, synthesis
 // One (task, column block): out_o = in[skel_o] + T_o in[red_o] for the task's outputs.  The
 // input block is staged in `lds` (K x (NT + 2) doubles, then the index lists).
@@ -238,18 +302,9 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
   if (io.on() && tk.mp >= 0) {
     const PairDesc pd = pairs[tk.mp];
-    for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0,
-                       [&](int j, int c, const double* a, bool imag0) {
-                         xs[j * LD + c] = (a && !imag0) ? *a : 0.0;
-                       });
+    gather_leaf_block<NT, LD>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0, xs);
   } else {
-    const double* src = in + static_cast<long long>(tk.in_row) * R + c0;
-    for (int e = threadIdx.x; e < K * (NT / 2); e += 256) {
-      const int row = e / (NT / 2), c2 = e % (NT / 2);
-      const double2 v = *reinterpret_cast<const double2*>(src + static_cast<long long>(row) * R + 2 * c2);
-      xs[row * LD + 2 * c2] = v.x;
-      xs[row * LD + 2 * c2 + 1] = v.y;
-    }
+    stage_rows<NT, LD>(in + static_cast<long long>(tk.in_row) * R + c0, K, R, xs);
   }
   if (k0 > 0)
     for (int e = threadIdx.x; e < K; e += 256) ix[e] = idx[tk.idx[0] + e];
@@ -289,7 +344,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
     }
     const int i0 = mt0 * 16 + lc, i1 = i0 + 16;
     // factor fragments are fetched PF K-steps ahead (double-buffered in registers)
-    constexpr int PF = 4;
+    constexpr int PF = kPrefetch;
     const int nsteps = (nr + 3) >> 2;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
     auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1) {
@@ -414,7 +469,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
 #pragma unroll
         for (int n = 0; n < NTL; ++n) acc[u][n].zero();
       const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
-      constexpr int PF = 4;
+      constexpr int PF = kPrefetch;
       const int nsteps = (k + 3) >> 2;
       AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
       double bc[PF][NTL], bn[PF][NTL];
@@ -479,15 +534,15 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
       }
     }
     const double* wrow = win + static_cast<long long>(tk.out_row[o]) * R + c0;
-    for (int e = threadIdx.x; e < k * NT; e += 256) {
-      const int i = e / NT, c = e % NT;
-      double* dst = acc_l + static_cast<int>(skel[i]) * LD + c;
-      const double val = wrow[static_cast<long long>(i) * R + c];
-      if (o == 0)
-        *dst = val;
-      else
-        *dst += val;
-    }
+    staged<double>(
+        k * NT, [&](int e) { return wrow[static_cast<long long>(e / NT) * R + e % NT]; },
+        [&](int e, double val) {
+          double* dst = acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT;
+          if (o == 0)
+            *dst = val;
+          else
+            *dst += val;
+        });
     __syncthreads();
   }
   if (io.on() && tk.mp >= 0) {
@@ -534,17 +589,8 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
   const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
   double* w0 = lds;
   double* w1 = lds + k0 * LD;
-  for (int p = 0; p < 2; ++p) {
-    const int k = p ? k1 : k0;
-    double* w = p ? w1 : w0;
-    const double* src = V + static_cast<long long>(ft.in_row[p]) * R + c0;
-    for (int e = threadIdx.x; e < k * (NT / 2); e += 256) {
-      const int row = e / (NT / 2), c2 = e % (NT / 2);
-      const double2 v = *reinterpret_cast<const double2*>(src + static_cast<long long>(row) * R + 2 * c2);
-      w[row * LD + 2 * c2] = v.x;
-      w[row * LD + 2 * c2 + 1] = v.y;
-    }
-  }
+  stage_rows<NT, LD>(V + static_cast<long long>(ft.in_row[0]) * R + c0, k0, R, w0);
+  stage_rows<NT, LD>(V + static_cast<long long>(ft.in_row[1]) * R + c0, k1, R, w1);
   __syncthreads();
   if (PREC == PSPLIT) {
     column_scales<NT>(k0, [&](int r, int c) { return w0[r * LD + c]; }, red_s, colsc[0]);
@@ -569,7 +615,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
     const int i = mt * 16 + lc;
     const bool iin = i < h;
     // both parities in one prefetched loop: step s < n0 feeds E, the rest feed O
-    constexpr int PF = 4;
+    constexpr int PF = kPrefetch;
     const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 + n1;
     AFrag<PREC> ac[PF], an[PF];
     auto fetch = [&](int s0, AFrag<PREC>* d) {
@@ -677,15 +723,18 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     __syncthreads();
-    for (int e = threadIdx.x; e < ih * NT; e += 256) {
-      const int i = e / NT, c = e % NT;
-      const int row = ft.row0 + i0 + i;
-      const double gp = Yin[(ybase + l + row) * R + c0 + c];
-      const double gm = Yin[(ybase + l - 1 - row) * R + c0 + c];
-      const double sc = half * scale[row];
-      eo[0][i * LD + c] = (gp + gm) * sc;
-      eo[1][i * LD + c] = (gp - gm) * sc;
-    }
+    staged<double2>(
+        ih * NT,
+        [&](int e) {
+          const int row = ft.row0 + i0 + e / NT, c = e % NT;
+          return make_double2(Yin[(ybase + l + row) * R + c0 + c], Yin[(ybase + l - 1 - row) * R + c0 + c]);
+        },
+        [&](int e, double2 g) {
+          const int i = e / NT, c = e % NT;
+          const double sc = half * scale[ft.row0 + i0 + i];
+          eo[0][i * LD + c] = (g.x + g.y) * sc;
+          eo[1][i * LD + c] = (g.x - g.y) * sc;
+        });
     __syncthreads();
     if (PREC == PSPLIT) {
       column_scales<NT>(ih, [&](int r, int c) { return eo[0][r * LD + c]; }, red_s, colsc[0]);
@@ -703,7 +752,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       int bsc[NTL];
 #pragma unroll
       for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[p][n * 16 + lc] : 0;
-      constexpr int PF = 4;
+      constexpr int PF = kPrefetch;
       const int nsteps = (ih + 3) >> 2;
       AFrag<PREC> ac[PF], an[PF];
       auto fetch = [&](int s0, AFrag<PREC>* d) {
@@ -777,9 +826,8 @@ __global__ void k_transpose_blocks(const double* __restrict__ fac, double* __res
 
 // Row-aligned split of every stored matrix (column-major, `rows` x `cols`; transposed: the
 // stored block is cols x rows): hi = leading slice on the row's grid, lo = fp32 remainder.
-__global__ void k_split_rows(const double* __restrict__ src, float* __restrict__ hi,
-                             float* __restrict__ lo, const FactorBlock* __restrict__ blocks,
-                             int transposed) {
+__global__ void k_split_rows(const double* __restrict__ src, float2* __restrict__ hl,
+                             const FactorBlock* __restrict__ blocks, int transposed) {
   const FactorBlock b = blocks[blockIdx.x];
   const int nrows = transposed ? b.cols : b.rows;
   const int ncols = transposed ? b.rows : b.cols;
@@ -793,8 +841,7 @@ __global__ void k_split_rows(const double* __restrict__ src, float* __restrict__
       const long long i = b.off + static_cast<long long>(c) * nrows + r;
       const double x = src[i];
       const double x1 = ldexp(rint(ldexp(x, sh)), -sh);
-      hi[i] = static_cast<float>(x1);
-      lo[i] = static_cast<float>(x - x1);
+      hl[i] = make_float2(static_cast<float>(x1), static_cast<float>(x - x1));
     }
   }
 }
@@ -817,8 +864,7 @@ hipError_t allow_lds(const void* fn, size_t bytes) {
 }
 
 FacPtr fac_ptr(const sht_plan_s* P, bool transposed) {
-  return transposed ? FacPtr{P->d.fac_t, P->d.fac_t_hi, P->d.fac_t_lo}
-                    : FacPtr{P->d.fac, P->d.fac_hi, P->d.fac_lo};
+  return transposed ? FacPtr{P->d.fac_t, P->d.fac_t_hl} : FacPtr{P->d.fac, P->d.fac_hl};
 }
 
 template <int PREC>
@@ -1017,34 +1063,32 @@ hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock
 }
 
 hipError_t split_factors(sht_plan_s* P, hipStream_t s) {
-  if (P->d.fac_hi) return hipSuccess;
+  if (P->d.fac_hl) return hipSuccess;
   const size_t n = static_cast<size_t>(std::max<long long>(P->n_fac, 4));
-  float* bufs[4] = {nullptr, nullptr, nullptr, nullptr};
-  for (int b = 0; b < 4; ++b) {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&bufs[b]), n * sizeof(float));
+  float2* bufs[2] = {nullptr, nullptr};
+  for (int b = 0; b < 2; ++b) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&bufs[b]), n * sizeof(float2));
     if (e != hipSuccess) {
-      for (int q = 0; q < b; ++q) (void)hipFree(bufs[q]);
+      if (b) (void)hipFree(bufs[0]);
       return e;
     }
   }
   for (long long b0 = 0; b0 < P->n_blocks; b0 += 1 << 20) {
     const long long nb = std::min<long long>(1 << 20, P->n_blocks - b0);
     hipLaunchKernelGGL(k_split_rows, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, P->d.fac, bufs[0],
-                       bufs[1], P->d.blocks + b0, 0);
+                       P->d.blocks + b0, 0);
     hipLaunchKernelGGL(k_split_rows, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, P->d.fac_t,
-                       bufs[2], bufs[3], P->d.blocks + b0, 1);
+                       bufs[1], P->d.blocks + b0, 1);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    for (float* q : bufs) (void)hipFree(q);
+    for (float2* q : bufs) (void)hipFree(q);
     return e;
   }
-  P->d.fac_hi = bufs[0];
-  P->d.fac_lo = bufs[1];
-  P->d.fac_t_hi = bufs[2];
-  P->d.fac_t_lo = bufs[3];
-  P->stats.device_bytes += static_cast<long long>(4 * n * sizeof(float));
+  P->d.fac_hl = bufs[0];
+  P->d.fac_t_hl = bufs[1];
+  P->stats.device_bytes += static_cast<long long>(2 * n * sizeof(float2));
   return hipSuccess;
 }
 

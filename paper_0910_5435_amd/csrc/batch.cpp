@@ -149,7 +149,7 @@ int build_set(sht_batch_s* B, int si, int nt, int nq, SetDev& out, std::vector<B
     BatchGroupDev d{};
     d.tasks = P->d.tasks;
     d.finals = P->d.finals;
-    d.fp = trans ? FacPtr{P->d.fac_t, P->d.fac_t_hi, P->d.fac_t_lo} : FacPtr{P->d.fac, P->d.fac_hi, P->d.fac_lo};
+    d.fp = trans ? FacPtr{P->d.fac_t, P->d.fac_t_hl} : FacPtr{P->d.fac, P->d.fac_hl};
     d.idx = P->d.idx;
     d.pairs = P->d.pairs;
     d.rowscale = B->op == SHT_BATCH_ANALYZE ? P->d.D : P->d.invD;

@@ -18,9 +18,12 @@ namespace sht {
 namespace {
 
 constexpr int kFftThreads = 256;
+constexpr int kBatch = 8;  // global loads in flight per thread while staging a row
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
+
+inline size_t fft_lds_bytes(int N) { return sizeof(double2) * static_cast<size_t>(N); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double wr, double wi) {
   return make_double2(a.x * wr - a.y * wi, a.x * wi + a.y * wr);
@@ -99,23 +102,33 @@ k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* con
   if (!ring_field(L2, F, ring, f)) return;
   const int N = 4 * l;
   const int logN = 31 - __clz(N);
-  for (int b = threadIdx.x; b < N; b += kFftThreads) {
-    double2 v = make_double2(0.0, 0.0);
-    if (b < L2) {
-      const long long row = static_cast<long long>(b) * L2 + ring;
-      const double* src = Y + row * R + (kind == SHT_COMPLEX ? 4 * f : 2 * f);
-      v = *reinterpret_cast<const double2*>(src);
-    } else if (b > L2) {
-      const int m = N - b;
-      const long long row = static_cast<long long>(m) * L2 + ring;
-      if (kind == SHT_COMPLEX) {
-        v = *reinterpret_cast<const double2*>(Y + row * R + 4 * f + 2);
-      } else {
-        const double2 g = *reinterpret_cast<const double2*>(Y + row * R + 2 * f);
-        v = make_double2(g.x, -g.y);  // g_{-m} = conj(g_m) for real fields
+  // gathers in batches of kBatch per thread, all issued before the LDS stores
+  for (int b0 = threadIdx.x; b0 < N; b0 += kFftThreads * kBatch) {
+    double2 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int b = b0 + u * kFftThreads;
+      v[u] = make_double2(0.0, 0.0);
+      if (b < L2) {
+        const long long row = static_cast<long long>(b) * L2 + ring;
+        const double* src = Y + row * R + (kind == SHT_COMPLEX ? 4 * f : 2 * f);
+        v[u] = *reinterpret_cast<const double2*>(src);
+      } else if (b > L2 && b < N) {
+        const int m = N - b;
+        const long long row = static_cast<long long>(m) * L2 + ring;
+        if (kind == SHT_COMPLEX) {
+          v[u] = *reinterpret_cast<const double2*>(Y + row * R + 4 * f + 2);
+        } else {
+          const double2 g = *reinterpret_cast<const double2*>(Y + row * R + 2 * f);
+          v[u] = make_double2(g.x, -g.y);  // g_{-m} = conj(g_m) for real fields
+        }
       }
     }
-    X[bitrev(b, logN)] = v;
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int b = b0 + u * kFftThreads;
+      if (b < N) X[bitrev(b, logN)] = v[u];
+    }
   }
   fft_lds(X, N, logN, tw, 1.0);
   double* gb = field_grid(grid, fptr, f, l, kind);
@@ -139,13 +152,23 @@ k_fft_analyze(const double* __restrict__ grid, double* const* __restrict__ fptr,
   const int logN = 31 - __clz(N);
   const double* gb = field_grid(const_cast<double*>(grid), fptr, f, l, kind);
   const long long rowbase = static_cast<long long>(ring) * N;
-  for (int j = threadIdx.x; j < N; j += kFftThreads) {
-    double2 v;
-    if (kind == SHT_COMPLEX)
-      v = reinterpret_cast<const double2*>(gb)[rowbase + j];
-    else
-      v = make_double2(gb[rowbase + j], 0.0);
-    X[bitrev(j, logN)] = v;
+  for (int j0 = threadIdx.x; j0 < N; j0 += kFftThreads * kBatch) {
+    double2 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int j = j0 + u * kFftThreads;
+      if (j >= N)
+        v[u] = make_double2(0.0, 0.0);
+      else if (kind == SHT_COMPLEX)
+        v[u] = reinterpret_cast<const double2*>(gb)[rowbase + j];
+      else
+        v[u] = make_double2(gb[rowbase + j], 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int j = j0 + u * kFftThreads;
+      if (j < N) X[bitrev(j, logN)] = v[u];
+    }
   }
   fft_lds(X, N, logN, tw, -1.0);
   for (int m = threadIdx.x; m < L2; m += kFftThreads) {
@@ -190,7 +213,7 @@ unsigned fft_grid(int l, int F) {
 }  // namespace
 
 hipError_t fft_prepare(int l) {
-  const size_t bytes = sizeof(double2) * 4 * static_cast<size_t>(l);
+  const size_t bytes = fft_lds_bytes(4 * l);
   hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), bytes);
   if (e == hipSuccess) e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), bytes);
   return e;
@@ -199,9 +222,9 @@ hipError_t fft_prepare(int l) {
 hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
                             hipStream_t s, double* const* fptr) {
   const int N = 4 * P->l;
-  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), sizeof(double2) * N);
+  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_synth), fft_lds_bytes(N));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_synth, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
+  hipLaunchKernelGGL(k_fft_synth, dim3(fft_grid(P->l, F)), dim3(kFftThreads), fft_lds_bytes(N), s,
                      y, grid, fptr, P->d.twiddle, P->l, R, F, P->kind);
   return hipGetLastError();
 }
@@ -209,9 +232,9 @@ hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, 
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
                               double scale, double real_pos, hipStream_t s, double* const* fptr) {
   const int N = 4 * P->l;
-  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), sizeof(double2) * N);
+  hipError_t e = allow_lds_fft(reinterpret_cast<const void*>(&k_fft_analyze), fft_lds_bytes(N));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fft_analyze, dim3(fft_grid(P->l, F)), dim3(kFftThreads), sizeof(double2) * N, s,
+  hipLaunchKernelGGL(k_fft_analyze, dim3(fft_grid(P->l, F)), dim3(kFftThreads), fft_lds_bytes(N), s,
                      grid, fptr, y, P->d.twiddle, P->l, R, F, P->kind, scale, real_pos);
   return hipGetLastError();
 }

@@ -511,8 +511,8 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
 }
 
 void free_plan_device(sht_plan_s* P) {
-  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hi, P->d.fac_lo, P->d.fac_t_hi,
-                  P->d.fac_t_lo, P->d.blocks, P->d.idx,    P->d.tasks,  P->d.finals,
+  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hl, P->d.fac_t_hl,
+                  P->d.blocks, P->d.idx,    P->d.tasks,  P->d.finals,
                   P->d.pairs,  P->d.invD,     P->d.D,      P->d.twiddle};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -71,10 +71,9 @@ struct FactorBlock {
 struct DeviceFactors {
   double* fac = nullptr;       // T and S entries (FP64), column-major, read by synthesis
   double* fac_t = nullptr;     // the same matrices transposed (same offsets), read by analysis
-  float* fac_hi = nullptr;     // split copies (first use of a split/FP32 transform): leading
-  float* fac_lo = nullptr;     // slice on each row's grid and the FP32 remainder, synthesis
-  float* fac_t_hi = nullptr;   // the same for the transposed copies
-  float* fac_t_lo = nullptr;
+  float2* fac_hl = nullptr;    // split copies (first use of a split/FP32 transform): per entry
+                               // the leading slice on its row's grid and the FP32 remainder
+  float2* fac_t_hl = nullptr;  // the same for the transposed copies
   FactorBlock* blocks = nullptr;  // every stored matrix (offset, rows, cols)
   uint16_t* idx = nullptr;     // skel/red index lists
   LevelTask* tasks = nullptr;  // all level tasks, step by step
@@ -118,9 +117,8 @@ struct LaunchClass {
 
 // Factor entries in the orientation a transform reads: FP64, and the split copies.
 struct FacPtr {
-  const double* d;  // FP64 entries
-  const float* hi;  // split: leading slice, row-aligned
-  const float* lo;  // split: fp32 remainder
+  const double* d;   // FP64 entries
+  const float2* hl;  // split: (leading slice on the row's grid, fp32 remainder) per entry
 };
 
 // Where a leaf task's vector rows live when they are read from / written to the caller's
