@@ -17,8 +17,8 @@ namespace sht {
 
 namespace {
 
-constexpr int kFftThreads = 256;
-constexpr int kBatch = 8;  // global loads in flight per thread while staging a row
+constexpr int kFftThreads = 1024;
+constexpr int kBatch = 2;  // global loads in flight per thread while staging a row
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
