@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
                     help="bandlimits of the mixed workload (uniform draw); the full set 64..2048 needs "
                          "about 210 GB for its inputs and outputs alone")
+    ap.add_argument("--no-gemm-baseline", action="store_true",
+                    help="skip the direct FP64 Legendre GEMM (library DGEMM on dense Q) comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 2 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -182,6 +184,54 @@ def time_per_field(plan, beta, steps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+def gemm_baseline(plan, l, R, steps):
+    """Direct FP64 Legendre step on the library DGEMM (torch.bmm): every dense Q^(m,p),
+    generated on the device by the plan's column kernel, applied to R columns in synthesis
+    (Q X) and in analysis (Q^T Y).  Pairs are taken in runs of 128 consecutive (m, p), each
+    run padded to its largest column count n_p.  Returns times per direction."""
+    import torch
+
+    npair = 4 * l
+    ncols = [max(0, (2 * l - mp // 2 - mp % 2 + 1) // 2) for mp in range(npair)]
+    Q = torch.zeros((npair, l, l), dtype=torch.float64, device="cuda")
+    for mp0 in range(0, npair, 256):
+        plan.dense_q(Q[mp0:], mp0, min(256, npair - mp0))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    Xt = torch.randn((npair, R, l), dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.randn((npair, l, R), dtype=torch.float64, device="cuda", generator=g)
+    runs = [(a, min(npair, a + 128)) for a in range(0, npair, 128)]
+    runs = [(a, b, max(ncols[a:b])) for a, b in runs if max(ncols[a:b]) > 0]
+
+    def synth():
+        for a, b, n in runs:
+            torch.bmm(Xt[a:b, :, :n], Q[a:b, :n, :])
+
+    def analysis():
+        for a, b, n in runs:
+            torch.bmm(Q[a:b, :n, :], Y[a:b])
+
+    out = {}
+    for name, fn in (("synth", synth), ("analysis", analysis)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / steps
+    dense = sum(l * n for n in ncols)
+    padded = sum((b - a) * l * n for a, b, n in runs)
+    out.update({"dense_entries": dense, "padded_entries": padded,
+                "tflops_synth": 2.0 * padded * R / (out["synth_ms"] / 1e3) / 1e12,
+                "tflops_analysis": 2.0 * padded * R / (out["analysis_ms"] / 1e3) / 1e12})
+    del Q, Xt, Y
+    torch.cuda.empty_cache()
+    return out
 
 
 def stage_totals(prof, steps):
@@ -365,9 +415,12 @@ def main():
         for prec in ("fp64", "split32", "fp32"):
             if prec == args.precision:
                 continue
-            ms_v, per_v, _, _ = time_pairs(plan, prec, beta, grid, back, args.steps, args.warmup)
+            ms_v, per_v, _, prof_v = time_pairs(plan, prec, beta, grid, back, args.steps, args.warmup,
+                                                profile=prec == "fp64")
             variants[prec] = {"value": F * args.steps / (ms_v / 1e3), "ms_per_step": ms_v / args.steps,
                               "ms_per_step_median": float(np.median(per_v))}
+            if prof_v:
+                variants[prec]["stages_ms_per_step"] = stage_totals(prof_v, args.steps)
             print(f"# {prec}: {variants[prec]['value']:.1f} pairs/s", file=sys.stderr, flush=True)
         if args.per_field_steps > 0:
             ms_pf = time_per_field(plan, beta, args.per_field_steps)
@@ -376,6 +429,18 @@ def main():
                                           "note": f"{F} single-field calls per direction per step"}
             print(f"# fp64 per field: {variants['fp64_per_field']['value']:.1f} pairs/s", file=sys.stderr,
                   flush=True)
+
+    gemm = None
+    if not args.no_gemm_baseline and "fp64" in variants:
+        gemm = gemm_baseline(plan, l, 4 * F, max(2, min(args.steps, 5)))
+        st64 = variants["fp64"]["stages_ms_per_step"]
+        bf = {d: sum(v for k, v in st64.items() if k.startswith(d + ".") and ".fft/" not in k)
+              for d in ("synth", "analysis")}
+        fft = sum(v for k, v in st64.items() if ".fft/" in k)
+        gemm["butterfly_fp64_legendre_ms"] = bf
+        gemm["pairs_per_s_with_fft"] = F / ((gemm["synth_ms"] + gemm["analysis_ms"] + fft) / 1e3)
+        print(f"# dense DGEMM Legendre: synth {gemm['synth_ms']:.1f} ms, analysis {gemm['analysis_ms']:.1f} ms "
+              f"(butterfly FP64 {bf['synth']:.1f} / {bf['analysis']:.1f} ms)", file=sys.stderr, flush=True)
 
     # per-field error of each precision against the FP64 butterfly on the full batch: synthesis
     # of the bench coefficients, and analysis of the FP64 grid
@@ -412,6 +477,7 @@ def main():
                    "eps": args.eps},
         "roofline": roofline(prof, ms_total, args.precision),
         "variants": variants,
+        "dense_gemm_fp64": gemm,
         "err_vs_fp64": err64,
         "round_trip_rel_err_max": float(np.max(err_rt)),
         "t_plan_s": t_plan,

@@ -124,6 +124,7 @@ SIGNATURES = {
     "sht_num_coeffs": (_LL, [_I, _I]),
     "sht_gl_nodes": (_I, [_I, _DP, _DP]),
     "sht_plan_columns": (_I, [_P, _I, _I, _DP, _I]),
+    "sht_dense_q": (_I, [_P, _I, _I, _P, _LL, _P]),
     "sht_plan_tree": (_I, [_P, _I, _I, _IP, _IP]),
     "sht_bf_build": (_I, [_DP, _I, _I, _I, _I, _I, _D, ctypes.POINTER(_P)]),
     "sht_bf_destroy": (None, [_P]),

@@ -507,6 +507,75 @@ int sht_plan_columns(sht_plan_t plan, int m, int p, double* q, int ldq) {
   return rc;
 }
 
+int sht_dense_q(sht_plan_t plan, int mp0, int count, double* q, long long stride, void* stream) {
+  if (!plan || !q || count < 1 || mp0 < 0 || mp0 + count > 4 * plan->l ||
+      stride < static_cast<long long>(plan->l) * plan->l)
+    return SHT_EINVAL;
+  DeviceScope ds(plan->device);
+  if (!ds.ok()) return SHT_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int l = plan->l, C = plan->C;
+  std::vector<int> hm(count), hp(count), hn(count);
+  int nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    hm[i] = (mp0 + i) / 2;
+    hp[i] = (mp0 + i) % 2;
+    hn[i] = plan->n_cols[mp0 + i];
+    nmax = std::max(nmax, hn[i]);
+  }
+  if (nmax == 0) return SHT_OK;
+  std::vector<double> sw(l);
+  for (int i = 0; i < l; ++i) sw[i] = std::sqrt(2.0 * plan->wp[i]);
+  void *dm = nullptr, *dp = nullptr, *dn = nullptr, *dprev = nullptr, *dcur = nullptr,
+       *dexp = nullptr, *dout = nullptr, *dx = nullptr, *dsw = nullptr;
+  int rc = SHT_OK;
+  auto ok = [&](hipError_t e) {
+    if (e != hipSuccess && rc == SHT_OK) rc = SHT_EHIP;
+    return rc == SHT_OK;
+  };
+  const size_t nc = static_cast<size_t>(count);
+  if (ok(hipMalloc(&dm, 4 * nc)) && ok(hipMalloc(&dp, 4 * nc)) && ok(hipMalloc(&dn, 4 * nc)) &&
+      ok(hipMalloc(&dprev, 16 * nc * l)) && ok(hipMalloc(&dcur, 16 * nc * l)) &&
+      ok(hipMalloc(&dexp, 4 * nc * l)) && ok(hipMalloc(&dout, 8 * nc * C * l)) &&
+      ok(hipMalloc(&dx, 8 * static_cast<size_t>(l))) && ok(hipMalloc(&dsw, 8 * static_cast<size_t>(l))) &&
+      ok(hipMemcpy(dm, hm.data(), 4 * nc, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dp, hp.data(), 4 * nc, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dn, hn.data(), 4 * nc, hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dx, plan->xp.data(), 8 * static_cast<size_t>(l), hipMemcpyHostToDevice)) &&
+      ok(hipMemcpy(dsw, sw.data(), 8 * static_cast<size_t>(l), hipMemcpyHostToDevice))) {
+    ColumnBatch cb;
+    cb.npairs = count;
+    cb.l = l;
+    cb.C = C;
+    cb.d_m = static_cast<int*>(dm);
+    cb.d_p = static_cast<int*>(dp);
+    cb.d_ncols = static_cast<int*>(dn);
+    cb.d_prev = static_cast<double*>(dprev);
+    cb.d_cur = static_cast<double*>(dcur);
+    cb.d_exp = static_cast<int*>(dexp);
+    cb.d_out = static_cast<double*>(dout);
+    cb.d_x = static_cast<const double*>(dx);
+    cb.d_sw = static_cast<const double*>(dsw);
+    if (ok(legendre_seed(cb, s))) {
+      const int leaves = (nmax + C - 1) / C;
+      for (int c = 0; c < leaves && rc == SHT_OK; ++c) {
+        if (!ok(legendre_chunk(cb, c, s))) break;
+        for (int i = 0; i < count && rc == SHT_OK; ++i) {
+          const int width = std::min(C, hn[i] - c * C);
+          if (width <= 0) continue;
+          ok(hipMemcpyAsync(q + i * stride + static_cast<long long>(c) * C * l,
+                            static_cast<double*>(dout) + static_cast<size_t>(i) * C * l,
+                            8 * static_cast<size_t>(width) * l, hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    if (rc == SHT_OK) ok(hipStreamSynchronize(s));
+  }
+  for (void* ptr : {dm, dp, dn, dprev, dcur, dexp, dout, dx, dsw})
+    if (ptr) (void)hipFree(ptr);
+  return rc;
+}
+
 // ---- host-only builder -------------------------------------------------------------------
 
 int sht_bf_build(const double* a, int rows, int cols, int lda, int leaf_width, int levels,

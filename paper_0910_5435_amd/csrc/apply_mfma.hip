@@ -118,12 +118,11 @@ struct Acc<PSPLIT> {
     cr = ex;
   }
   __device__ void set(int e, double x) { hi[e] = x; }
-  // one K-step from zero (every K-step is flushed): the exact leading sum of four products,
-  // then the corrections, smallest first
+  // one K-step (flushed after every K-step): the exact leading sum of four products, then
+  // the corrections, smallest first
   __device__ void step(const AFrag<PSPLIT>& a, const BFrag<PSPLIT>& b) {
-    const f4 z = {0.f, 0.f, 0.f, 0.f};
-    ex = mfma32(a.a1, b.b1, z);
-    cr = mfma32(a.a2, b.b2, z);
+    ex = mfma32(a.a1, b.b1, ex);
+    cr = mfma32(a.a2, b.b2, cr);
     cr = mfma32(a.a2, b.b1, cr);
     cr = mfma32(a.a1, b.b2, cr);
   }
@@ -224,20 +223,19 @@ __device__ __forceinline__ void for_leaf_block(const CoefIO& io, int m, int p, i
   }
 }
 
-// Staging loop with the global loads of kB items per thread issued before any of them is
+// Staging loop with the global loads of B items per thread issued before any of them is
 // used: v = load(e), then put(e, v), for e = threadIdx.x + 256 i < n.
-constexpr int kStage = 8;
-template <typename T, typename Load, typename Put>
+template <typename T, int B = 8, typename Load, typename Put>
 __device__ __forceinline__ void staged(int n, Load&& load, Put&& put) {
-  for (int e0 = threadIdx.x; e0 < n; e0 += 256 * kStage) {
-    T v[kStage];
+  for (int e0 = threadIdx.x; e0 < n; e0 += 256 * B) {
+    T v[B];
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
+    for (int u = 0; u < B; ++u) {
       const int e = e0 + u * 256;
       if (e < n) v[u] = load(e);
     }
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
+    for (int u = 0; u < B; ++u) {
       const int e = e0 + u * 256;
       if (e < n) put(e, v[u]);
     }
@@ -270,7 +268,7 @@ __device__ __forceinline__ void gather_leaf_block(const CoefIO& io, int m, int p
 // rows x NT block of an R-wide row buffer (first row `src`) into LDS rows of stride LD.
 template <int NT, int LD>
 __device__ __forceinline__ void stage_rows(const double* __restrict__ src, int rows, int R, double* dst) {
-  staged<double2>(
+  staged<double2, 4>(
       rows * (NT / 2),
       [&](int e) {
         const int row = e / (NT / 2), c2 = e % (NT / 2);
@@ -723,7 +721,8 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     __syncthreads();
-    staged<double2>(
+    // two items in flight: this kernel keeps up to 24 accumulator tiles per wave in registers
+    staged<double2, 2>(
         ih * NT,
         [&](int e) {
           const int row = ft.row0 + i0 + e / NT, c = e % NT;

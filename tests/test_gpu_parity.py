@@ -192,3 +192,18 @@ def test_split_precision_needs_matrix_core_widths():
     with pytest.raises(_lib.ShtError) as ei:
         P.synth(beta, precision="split32")
     assert ei.value.status == _lib.SHT_EUNSUPPORTED
+
+
+def test_dense_q_export_matches_oracle():
+    # the comparison baseline's dense matrices come from the same column kernel
+    l = 16
+    P = _plan(l, 4)
+    Q = torch.zeros((4 * l, l, l), dtype=torch.float64, device="cuda")
+    P.dense_q(Q)
+    Qh = Q.cpu().numpy()
+    for mp in range(4 * l):
+        m, p = mp // 2, mp % 2
+        ref = oracle.dense_q(l, m, p)  # l x n_p
+        n = ref.shape[1]
+        np.testing.assert_allclose(Qh[mp][:n].T, ref, atol=2e-14)
+        assert np.all(Qh[mp][n:] == 0)
