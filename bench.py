@@ -50,9 +50,10 @@ def parse():
     ap.add_argument("--cpu-orders", type=int, default=24)
     ap.add_argument("--cpu-fields", type=int, default=4,
                     help="fields in the oracle sample (a multiple of 4 for the matrix-core variants)")
-    ap.add_argument("--workload", default="metric", choices=["metric", "mixed"],
+    ap.add_argument("--workload", default="metric", choices=["metric", "mixed", "single"],
                     help="metric: the l=1024, 64-field line; mixed: 96 requests of mixed bandlimits "
-                         "through the batched persistent launch, beside one call per request")
+                         "through the batched persistent launch, beside one call per request; single: "
+                         "one complex field at l=256 in FP64 (the factor-streaming regime)")
     ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
                     help="bandlimits of the mixed workload (uniform draw); the full set 64..2048 needs "
                          "about 210 GB for its inputs and outputs alone")
@@ -375,6 +376,13 @@ def main():
         sys.exit(2)
     if args.workload == "mixed":
         return mixed(args)
+    metric = METRIC
+    if args.workload == "single":
+        # one complex field, l = 256, FP64 butterfly (vector kernels at R = 4): the oracle runs
+        # on every order
+        args.l, args.fields, args.precision, args.no_variants = 256, 1, "fp64", True
+        args.power, args.eps, args.cpu_fields, args.cpu_orders = 1.0, 1e-13, 1, 512
+        metric = "SHT synth+analysis pairs/s at l=256, 1 field, FP64 butterfly"
     import numpy as np
     import torch
 
@@ -431,9 +439,9 @@ def main():
                   flush=True)
 
     gemm = None
-    if not args.no_gemm_baseline and "fp64" in variants:
+    if not args.no_gemm_baseline and ("fp64" in variants or args.precision == "fp64"):
         gemm = gemm_baseline(plan, l, 4 * F, max(2, min(args.steps, 5)))
-        st64 = variants["fp64"]["stages_ms_per_step"]
+        st64 = variants["fp64"]["stages_ms_per_step"] if "fp64" in variants else stage_totals(prof, args.steps)
         bf = {d: sum(v for k, v in st64.items() if k.startswith(d + ".") and ".fft/" not in k)
               for d in ("synth", "analysis")}
         fft = sum(v for k, v in st64.items() if ".fft/" in k)
@@ -458,7 +466,7 @@ def main():
     torch.cuda.synchronize()
 
     out = {
-        "metric": METRIC,
+        "metric": metric,
         "value": value,
         "unit": "pairs/s",
         "n_gpus": 1,
