@@ -427,35 +427,41 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
   __shared__ double red_s[256];
-  __shared__ int colsc[2][NT];
+  __shared__ int colsc[NT];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
   const int nouts = tk.k[1] < 0 ? 1 : 2;
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
+  // LDS: the accumulated input block (K x LD), the current output block w_o (max k x LD),
+  // the index lists
+  // FP64 and FP32 read w_o straight from global memory (their loops are not VALU-bound and
+  // the smaller LDS block keeps 32-column tiles); the split form stages w_o in LDS once per
+  // work-group.
+  constexpr bool WLDS = PREC == PSPLIT;
   double* acc_l = lds;
-  uint16_t* ix = reinterpret_cast<uint16_t*>(acc_l + K * LD);  // [skel0 red0 skel1 red1]
+  double* wl = acc_l + K * LD;
+  uint16_t* ix = reinterpret_cast<uint16_t*>(wl + (WLDS ? (k0 > k1 ? k0 : k1) * LD : 0));  // [skel0 red0 skel1 red1]
   for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
-  if (PREC == PSPLIT) {
-    for (int o = 0; o < nouts; ++o) {
-      const double* wrow = win + static_cast<long long>(tk.out_row[o]) * R + c0;
-      column_scales<NT>(o ? k1 : k0, [&](int r, int c) { return wrow[static_cast<long long>(r) * R + c]; },
-                        red_s, colsc[o]);
-    }
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lc = lane & 15, lr = lane >> 4;
   for (int o = 0; o < nouts; ++o) {
     const int k = o ? k1 : k0;
     const int nr = K - k;
+    const double* wg = win + static_cast<long long>(tk.out_row[o]) * R + c0;  // w_o in global memory
+    if (WLDS) {
+      stage_rows<NT, LD>(wg, k, R, wl);
+      __syncthreads();
+      if (PREC == PSPLIT) column_scales<NT>(k, [&](int r, int c) { return wl[r * LD + c]; }, red_s, colsc);
+    } else {
+      __syncthreads();
+    }
     const uint16_t* skel = ix + o * K;
     const uint16_t* red = skel + k;
     const long long toff = tk.fac[o];  // T^T: nr x k column-major
-    const double* wb = win + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
     int bsc[NTL];
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[o][n * 16 + lc] : 0;
+    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[n * 16 + lc] : 0;
     const int nm = (nr + 15) >> 4;
     const int np = (nm + 1) >> 1;
     for (int q = wave; q < np; q += 4) {
@@ -470,7 +476,8 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
       constexpr int PF = kPrefetch;
       const int nsteps = (k + 3) >> 2;
       AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
-      double bc[PF][NTL], bn[PF][NTL];
+      constexpr int PB = WLDS ? 1 : PF;  // B fragments prefetched with A when read from global
+      double bc[PB][NTL], bn[PB][NTL];
       auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, double (*b)[NTL]) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -479,8 +486,11 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
           const long long base = toff + static_cast<long long>(i) * nr;
           d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr);
           d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr);
+          if (!WLDS) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) b[u][n] = iin ? wb[static_cast<long long>(i) * R + n * 16] : 0.0;
+            for (int n = 0; n < NTL; ++n)
+              b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
+          }
         }
       };
       fetch(0, a0c, a1c, bc);
@@ -488,9 +498,13 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
+          const int i = (s0 + u) * 4 + lr;
+          const bool iin = i < k;
+          const double* wr = wl + (iin ? i : 0) * LD + lc;
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
-            const BFrag<PREC> b = make_b<PREC>(bc[u][n], bsc[n]);
+            const double x = WLDS ? (iin ? wr[n * 16] : 0.0) : bc[u % PB][n];
+            const BFrag<PREC> b = make_b<PREC>(x, bsc[n]);
             acc[0][n].step(a0c[u], b);
             if (two) acc[1][n].step(a1c[u], b);
           }
@@ -509,8 +523,12 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         for (int u = 0; u < PF; ++u) {
           a0c[u] = a0n[u];
           a1c[u] = a1n[u];
+        }
+        if (!WLDS) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
+          for (int u = 0; u < PB; ++u)
+#pragma unroll
+            for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
         }
       }
 #pragma unroll
@@ -531,16 +549,27 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         }
       }
     }
-    const double* wrow = win + static_cast<long long>(tk.out_row[o]) * R + c0;
-    staged<double>(
-        k * NT, [&](int e) { return wrow[static_cast<long long>(e / NT) * R + e % NT]; },
-        [&](int e, double val) {
-          double* dst = acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT;
-          if (o == 0)
-            *dst = val;
-          else
-            *dst += val;
-        });
+    // identity part: w_o at the skeleton rows (disjoint from the redundant rows above)
+    if (WLDS) {
+      for (int e = threadIdx.x; e < k * NT; e += 256) {
+        const int i = e / NT, c = e % NT;
+        double* dst = acc_l + static_cast<int>(skel[i]) * LD + c;
+        if (o == 0)
+          *dst = wl[i * LD + c];
+        else
+          *dst += wl[i * LD + c];
+      }
+    } else {
+      staged<double>(
+          k * NT, [&](int e) { return wg[static_cast<long long>(e / NT) * R + e % NT]; },
+          [&](int e, double val) {
+            double* dst = acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT;
+            if (o == 0)
+              *dst = val;
+            else
+              *dst += val;
+          });
+    }
     __syncthreads();
   }
   if (io.on() && tk.mp >= 0) {
@@ -874,11 +903,13 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
   // LDS holds the task's K x NT input block: 32 columns while that stays within 100 KiB
-  const int NT = (R % 32 == 0 && static_cast<long long>(K) * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
-  if (static_cast<long long>(K) * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
+  // rows held in LDS: the input block, plus (transposed) the current output block
+  const long long rows = K + (transpose && PREC == PSPLIT ? lc.maxk : 0);
+  const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
+  if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
-  const size_t lds = static_cast<size_t>(K) * (NT + 2) * 8 + 4 * static_cast<size_t>(K) + 16;
+  const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 4 * static_cast<size_t>(K) + 16;
   const FacPtr fp = fac_ptr(P, transpose);
   hipError_t e;
 #define LEVEL_LAUNCH(KER)                                                                              \

@@ -113,10 +113,13 @@ void free_batch(sht_batch_s* B) {
 }
 
 // Largest input length of any level task and dynamic LDS of one item of a group.
-size_t group_lds(const sht_plan_s* P, int nt, bool trans) {
-  int maxK = 0;
+size_t group_lds(const sht_plan_s* P, int nt, bool trans, int precision) {
+  int maxK = 0, maxk = 0;
   for (int v : P->step_maxK) maxK = std::max(maxK, v);
-  size_t lds = static_cast<size_t>(maxK) * (nt + 2) * 8 + 4 * static_cast<size_t>(maxK) + 16;
+  for (int v : P->step_maxk) maxk = std::max(maxk, v);
+  // transposed level items of the split form also hold their current output block
+  const size_t rows = static_cast<size_t>(maxK) + (trans && precision == SHT_SPLIT32 ? maxk : 0);
+  size_t lds = rows * (nt + 2) * 8 + 4 * static_cast<size_t>(maxK) + 16;
   if (trans)
     lds = std::max(lds, final_trans_lds_bytes());
   else
@@ -145,7 +148,7 @@ int build_set(sht_batch_s* B, int si, int nt, int nq, SetDev& out, std::vector<B
     const int R = round_up(col_width(P) * g.F, nt);
     const int Rf = trans ? round_up(col_width(P) * g.F, 16) : R;
     if (Rf > R) return SHT_EINTERNAL;
-    lds = std::max(lds, group_lds(P, nt, trans));
+    lds = std::max(lds, group_lds(P, nt, trans, B->precision));
     BatchGroupDev d{};
     d.tasks = P->d.tasks;
     d.finals = P->d.finals;
