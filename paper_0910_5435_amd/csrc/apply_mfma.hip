@@ -40,6 +40,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kXcd = 8;
 constexpr int kSliceBits = 11;  // |x1| <= 2^11 units of the row / column grid
 constexpr int kPrefetch = 4;    // K-steps of factor fragments fetched ahead (double-buffered)
+// Work-groups per compute unit the apply kernels are compiled for: two keep two waves on
+// every SIMD (at most 256 registers per lane), so one wave's stalls are covered by another.
+constexpr int kMinBlocks = 2;
 
 enum { P64 = 0, PSPLIT = 1, P32 = 2 };
 
@@ -402,7 +405,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
 }
 
 template <int NT, int PREC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, kMinBlocks)
 k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
                    const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
                    const double* __restrict__ in, double* __restrict__ out, int R, CoefIO io) {
@@ -589,7 +592,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
 }
 
 template <int NT, int PREC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, kMinBlocks)
 k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
                    const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
                    const double* __restrict__ win, double* __restrict__ xout, int R, CoefIO io) {
@@ -706,7 +709,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
 }
 
 template <int NT, int PREC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, kMinBlocks)
 k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
                    const double* __restrict__ v0buf, const double* __restrict__ v1buf,
                    const double* __restrict__ invD, double* __restrict__ Y, int l, int R) {
@@ -830,7 +833,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
 }
 
 template <int NT, int ICH, int PREC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, kMinBlocks)
 k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
                    const double* __restrict__ Yin, const double* __restrict__ scale, double half,
                    double* __restrict__ v0buf, double* __restrict__ v1buf, int l, int R) {
