@@ -41,7 +41,8 @@ constexpr int kXcd = 8;
 constexpr int kSliceBits = 11;  // |x1| <= 2^11 units of the row / column grid
 constexpr int kPrefetch = 4;    // K-steps of factor fragments fetched ahead (double-buffered)
 // Work-groups per compute unit the apply kernels are compiled for: two keep two waves on
-// every SIMD (at most 256 registers per lane), so one wave's stalls are covered by another.
+// every SIMD (at most 256 registers per lane), so one wave's stalls are covered by another
+// (three made no difference where they fit without spilling).
 constexpr int kMinBlocks = 2;
 
 enum { P64 = 0, PSPLIT = 1, P32 = 2 };
