@@ -1032,7 +1032,7 @@ __device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* ld
 // queue (queue = work-group id mod nq: with nq = 8 the queue of its XCD, since work-groups are
 // dealt to the XCDs round-robin) and then from the others, one atomic increment per item.
 template <int NT, int PREC, bool TRANS>
-__global__ void __launch_bounds__(256) k_batch(BatchLaunch bl) {
+__global__ void __launch_bounds__(256, kMinBlocks) k_batch(BatchLaunch bl) {
   extern __shared__ double lds[];
   __shared__ int s_item;
   const int nq = bl.nq;
