@@ -65,21 +65,40 @@ template <> struct AFrag<P64> { double a; };
 template <> struct AFrag<PSPLIT> { float a1, a2; };
 template <> struct AFrag<P32> { float a; };
 
+// FP32 fragment loads are branch-free: the load always happens (from `safe`, an entry of the
+// same block, where ok is false) and the zero is selected afterwards, because a per-lane
+// condition around a load compiles to a divergent branch per K-step, which costs more than
+// the cheap FP32 MFMA it guards.  For FP64 and split FP32 the MFMA work per step is larger
+// and skipping the masked loads measured faster.
+template <int PREC> constexpr bool kBranchFree = PREC == P32;
+
+// Entry p[i] where ok holds, else 0 (branch-free for the precisions that ask for it).
+template <int PREC, class T>
+__device__ __forceinline__ T sel_load(const T* p, long long i, bool ok, long long safe) {
+  if constexpr (kBranchFree<PREC>) {
+    const T v = p[ok ? i : safe];
+    return ok ? v : T(0);
+  } else {
+    return ok ? p[i] : T(0);
+  }
+}
+
+// Factor fragment entry i, or 0 where ok is false; `safe` is an entry of the same block.
 template <int PREC>
-__device__ __forceinline__ AFrag<PREC> load_a(const FacPtr& f, long long i, bool ok);
+__device__ __forceinline__ AFrag<PREC> load_a(const FacPtr& f, long long i, bool ok, long long safe);
 template <>
-__device__ __forceinline__ AFrag<P64> load_a<P64>(const FacPtr& f, long long i, bool ok) {
+__device__ __forceinline__ AFrag<P64> load_a<P64>(const FacPtr& f, long long i, bool ok, long long) {
   return {ok ? f.d[i] : 0.0};
 }
 template <>
-__device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok) {
+__device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok, long long) {
   const float2 v = ok ? f.hl[i] : make_float2(0.0f, 0.0f);
   return {v.x, v.y};
 }
 template <>
-__device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok) {
-  const float2 v = ok ? f.hl[i] : make_float2(0.0f, 0.0f);
-  return {v.x + v.y};
+__device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok, long long safe) {
+  const float2 v = f.hl[ok ? i : safe];
+  return {ok ? v.x + v.y : 0.0f};
 }
 
 template <int PREC> struct BFrag;
@@ -315,7 +334,8 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
   __syncthreads();
   if (PREC == PSPLIT)
     column_scales<NT>(K, [&](int r, int c) { return xs[r * LD + c]; }, red_s, colsc);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
   int bsc[NTL];
 #pragma unroll
@@ -355,23 +375,26 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const int kk = (s0 + u) * 4 + lr;
         const bool kin = kk < nr;
         const long long base = toff + static_cast<long long>(kk) * k;
-        d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k);
-        d1[u] = load_a<PREC>(fp, base + i1, kin && two && i1 < k);
+        d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k, toff);
+        d1[u] = load_a<PREC>(fp, base + i1, kin && two && i1 < k, toff);
       }
     };
-    fetch(0, a0c, a1c);
+    // the branch-free loads read the block's first entry, which exists only when there is a step
+    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n);
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
         const bool kin = kk < nr;
-        const double* xr = xs + (kin ? red[kk] : 0) * LD + lc;
+        const int rr = kBranchFree<PREC> ? red[kin ? kk : 0] : (kin ? red[kk] : 0);
+        const double* xr = xs + rr * LD + lc;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          const BFrag<PREC> b = make_b<PREC>(kin ? xr[n * 16] : 0.0, bsc[n]);
+          const BFrag<PREC> b = make_b<PREC>(sel_load<PREC>(xr, n * 16, kin, n * 16), bsc[n]);
           acc[0][n].step(a0c[u], b);
-          if (two) acc[1][n].step(a1c[u], b);
+          // acc[1] sees zero fragments when !two; the branch-free form runs it anyway
+          if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
         }
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
@@ -447,7 +470,8 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
   uint16_t* ix = reinterpret_cast<uint16_t*>(wl + (WLDS ? (k0 > k1 ? k0 : k1) * LD : 0));  // [skel0 red0 skel1 red1]
   for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
   for (int o = 0; o < nouts; ++o) {
     const int k = o ? k1 : k0;
@@ -488,16 +512,22 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
           const int i = (s0 + u) * 4 + lr;
           const bool iin = i < k;
           const long long base = toff + static_cast<long long>(i) * nr;
-          d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr);
-          d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr);
+          d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr, toff);
+          d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr, toff);
           if (!WLDS) {
 #pragma unroll
-            for (int n = 0; n < NTL; ++n)
-              b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
+            for (int n = 0; n < NTL; ++n) {
+              if constexpr (kBranchFree<PREC>) {  // row 0 stands in for rows past the block
+                const double wv = wg[static_cast<long long>(iin ? i : 0) * R + n * 16 + lc];
+                b[u % PB][n] = iin ? wv : 0.0;
+              } else {
+                b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
+              }
+            }
           }
         }
       };
-      fetch(0, a0c, a1c, bc);
+      if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c, bc);
       for (int s0 = 0; s0 < nsteps; s0 += PF) {
         if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
 #pragma unroll
@@ -507,10 +537,10 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
           const double* wr = wl + (iin ? i : 0) * LD + lc;
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
-            const double x = WLDS ? (iin ? wr[n * 16] : 0.0) : bc[u % PB][n];
+            const double x = WLDS ? sel_load<PREC>(wr, n * 16, iin, n * 16) : bc[u % PB][n];
             const BFrag<PREC> b = make_b<PREC>(x, bsc[n]);
             acc[0][n].step(a0c[u], b);
-            if (two) acc[1][n].step(a1c[u], b);
+            if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
           }
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
@@ -627,7 +657,8 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
     column_scales<NT>(k0, [&](int r, int c) { return w0[r * LD + c]; }, red_s, colsc[0]);
     column_scales<NT>(k1, [&](int r, int c) { return w1[r * LD + c]; }, red_s, colsc[1]);
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
   int bsc[2][NTL];
 #pragma unroll
@@ -648,6 +679,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
     // both parities in one prefetched loop: step s < n0 feeds E, the rest feed O
     constexpr int PF = kPrefetch;
     const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 + n1;
+    const long long safe = k0 > 0 ? ft.fac[0] : ft.fac[1];  // a non-empty block when nsteps > 0
     AFrag<PREC> ac[PF], an[PF];
     auto fetch = [&](int s0, AFrag<PREC>* d) {
 #pragma unroll
@@ -656,10 +688,10 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         const bool odd = st >= n0;
         const int a = (odd ? st - n0 : st) * 4 + lr;
         const bool ain = st < nsteps && a < (odd ? k1 : k0);
-        d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin);
+        d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin, safe);
       }
     };
-    fetch(0, ac);
+    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, ac);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
       if (s0 + PF < nsteps) fetch(s0 + PF, an);
 #pragma unroll
@@ -672,12 +704,12 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc;
         if (!odd) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], make_b<PREC>(ain ? wr[n * 16] : 0.0, bsc[0][n]));
+          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], make_b<PREC>(sel_load<PREC>(wr, n * 16, ain, n * 16), bsc[0][n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) E[n].flush_step();
         } else {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], make_b<PREC>(ain ? wr[n * 16] : 0.0, bsc[1][n]));
+          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], make_b<PREC>(sel_load<PREC>(wr, n * 16, ain, n * 16), bsc[1][n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) O[n].flush_step();
         }
@@ -743,7 +775,8 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   double* V = ft.vbuf ? v1buf : v0buf;
   const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
   const long long ybase = static_cast<long long>(ft.m) * 2 * l;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
   Acc<PREC> acc[MAXT][NTL];
@@ -791,10 +824,10 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
-          d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k);
+          d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k, soff);
         }
       };
-      fetch(0, ac);
+      if (!kBranchFree<PREC> || nsteps > 0) fetch(0, ac);
       for (int s0 = 0; s0 < nsteps; s0 += PF) {
         if (s0 + PF < nsteps) fetch(s0 + PF, an);
 #pragma unroll
@@ -803,7 +836,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
           const bool iin = i < ih;
           const double* er = src + (iin ? i : 0) * LD + lc;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], make_b<PREC>(iin ? er[n * 16] : 0.0, bsc[n]));
+          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], make_b<PREC>(sel_load<PREC>(er, n * 16, iin, n * 16), bsc[n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) acc[u][n].flush_step();
         }
@@ -1047,7 +1080,7 @@ __global__ void __launch_bounds__(256, kMinBlocks) k_batch(BatchLaunch bl) {
       for (;;) {
         if (threadIdx.x == 0) s_item = beg + static_cast<int>(atomicAdd(&heads[ph * nq + q], 1u));
         __syncthreads();
-        const int i = s_item;
+        const int i = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar item loads
         __syncthreads();
         if (i >= end) break;
         const BatchItem it = bl.items[i];
