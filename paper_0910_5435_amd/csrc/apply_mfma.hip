@@ -332,11 +332,15 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 }
 
 // ------------------------------------------------------------------ level, transposed
-// LDS holds the accumulated input block (K x NT) and the index lists; the vectors w_o of
-// the output blocks are read as B fragments straight from global memory (prefetched with
-// the factor fragments).  Output block o contributes T_o^T w_o at rows red_o and w_o at
-// rows skel_o (assigned for o = 0, added for o = 1; every row gets exactly one term per
-// block).
+// Output block o contributes T_o^T w_o at rows red_o and w_o at rows skel_o; every input row
+// gets exactly one term from each block.  Both blocks run at once (their row-tile pairs are
+// dealt to the waves together, as in the synthesis kernel) and every term is added into the
+// zeroed LDS block with an LDS atomic add: a row receives at most two terms, and 0 + a + b
+// gives the same bits in either order, so the result does not depend on timing.
+// LDS: the accumulated input block (K x NT), for the split form the vectors w_0 and w_1
+// (k_0 + k_1 rows, cut on the fly from their own column scales), then the index lists.  FP64
+// and FP32 read w_o as B fragments straight from global memory (prefetched with the factor
+// fragments): their loops are not VALU-bound and the smaller LDS block keeps 32-column tiles.
 template <int NT, int PREC>
 __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
@@ -344,159 +348,150 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const CoefIO& io, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
+  constexpr bool WLDS = PREC == PSPLIT;
   __shared__ double red_s[256];
-  __shared__ int colsc[NT];
+  __shared__ int colsc[2][NT];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
   const int nouts = tk.k[1] < 0 ? 1 : 2;
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
-  // LDS: the accumulated input block (K x LD), the current output block w_o (max k x LD),
-  // the index lists
-  // FP64 and FP32 read w_o straight from global memory (their loops are not VALU-bound and
-  // the smaller LDS block keeps 32-column tiles); the split form stages w_o in LDS once per
-  // work-group.
-  constexpr bool WLDS = PREC == PSPLIT;
   double* acc_l = lds;
-  double* wl = acc_l + K * LD;
-  uint16_t* ix = reinterpret_cast<uint16_t*>(wl + (WLDS ? (k0 > k1 ? k0 : k1) * LD : 0));  // [skel0 red0 skel1 red1]
+  double* wl0 = acc_l + K * LD;
+  double* wl1 = wl0 + (WLDS ? k0 * LD : 0);
+  uint16_t* ix = reinterpret_cast<uint16_t*>(wl1 + (WLDS ? k1 * LD : 0));  // [skel0 red0 skel1 red1]
   for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
+  for (int e = threadIdx.x; e < K * LD; e += 256) acc_l[e] = 0.0;
+  const double* wg0 = win + static_cast<long long>(tk.out_row[0]) * R + c0;
+  const double* wg1 = win + static_cast<long long>(nouts > 1 ? tk.out_row[1] : tk.out_row[0]) * R + c0;
+  if (WLDS) {
+    stage_rows<NT, LD>(wg0, k0, R, wl0);
+    if (nouts > 1) stage_rows<NT, LD>(wg1, k1, R, wl1);
+  }
+  __syncthreads();
+  if (PREC == PSPLIT) {
+    column_scales<NT>(k0, [&](int r, int c) { return wl0[r * LD + c]; }, red_s, colsc[0]);
+    if (nouts > 1) column_scales<NT>(k1, [&](int r, int c) { return wl1[r * LD + c]; }, red_s, colsc[1]);
+  }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
-  for (int o = 0; o < nouts; ++o) {
+  const int nm0 = (K - k0 + 15) >> 4, nm1 = nouts > 1 ? (K - k1 + 15) >> 4 : 0;
+  const int np0 = (nm0 + 1) >> 1, np1 = (nm1 + 1) >> 1;  // pairs of row tiles per output
+  for (int q = wave; q < np0 + np1; q += 4) {
+    const int o = q < np0 ? 0 : 1;
+    const int mt0 = 2 * (o ? q - np0 : q);
     const int k = o ? k1 : k0;
     const int nr = K - k;
-    const double* wg = win + static_cast<long long>(tk.out_row[o]) * R + c0;  // w_o in global memory
-    if (WLDS) {
-      stage_rows<NT, LD>(wg, k, R, wl);
-      __syncthreads();
-      if (PREC == PSPLIT) column_scales<NT>(k, [&](int r, int c) { return wl[r * LD + c]; }, red_s, colsc);
-    } else {
-      __syncthreads();
-    }
-    const uint16_t* skel = ix + o * K;
-    const uint16_t* red = skel + k;
+    const bool two = mt0 + 1 < (o ? nm1 : nm0);
+    const uint16_t* red = ix + o * K + k;
     const long long toff = tk.fac[o];  // T^T: nr x k column-major
+    const double* wg = o ? wg1 : wg0;
+    const double* wl = o ? wl1 : wl0;
     int bsc[NTL];
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[n * 16 + lc] : 0;
-    const int nm = (nr + 15) >> 4;
-    const int np = (nm + 1) >> 1;
-    for (int q = wave; q < np; q += 4) {
-      const int mt0 = 2 * q;
-      const bool two = mt0 + 1 < nm;
-      Acc<PREC> acc[2][NTL];
+    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[o][n * 16 + lc] : 0;
+    Acc<PREC> acc[2][NTL];
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) acc[u][n].zero();
-      const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
-      constexpr int PF = kPrefetch;
-      const int nsteps = (k + 3) >> 2;
-      AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
-      constexpr int PB = WLDS ? 1 : PF;  // B fragments prefetched with A when read from global
-      double bc[PB][NTL], bn[PB][NTL];
-      auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, double (*b)[NTL]) {
+      for (int n = 0; n < NTL; ++n) acc[u][n].zero();
+    const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
+    constexpr int PF = kPrefetch;
+    const int nsteps = (k + 3) >> 2;
+    AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
+    constexpr int PB = WLDS ? 1 : PF;  // B fragments prefetched with A when read from global
+    double bc[PB][NTL], bn[PB][NTL];
+    auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, double (*b)[NTL]) {
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          const int i = (s0 + u) * 4 + lr;
-          const bool iin = i < k;
-          const long long base = toff + static_cast<long long>(i) * nr;
-          d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr, toff);
-          d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr, toff);
-          if (!WLDS) {
+      for (int u = 0; u < PF; ++u) {
+        const int i = (s0 + u) * 4 + lr;
+        const bool iin = i < k;
+        const long long base = toff + static_cast<long long>(i) * nr;
+        d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr, toff);
+        d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr, toff);
+        if (!WLDS) {
 #pragma unroll
-            for (int n = 0; n < NTL; ++n) {
-              if constexpr (kBranchFree<PREC>) {  // row 0 stands in for rows past the block
-                const double wv = wg[static_cast<long long>(iin ? i : 0) * R + n * 16 + lc];
-                b[u % PB][n] = iin ? wv : 0.0;
-              } else {
-                b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
-              }
+          for (int n = 0; n < NTL; ++n) {
+            if constexpr (kBranchFree<PREC>) {  // row 0 stands in for rows past the block
+              const double wv = wg[static_cast<long long>(iin ? i : 0) * R + n * 16 + lc];
+              b[u % PB][n] = iin ? wv : 0.0;
+            } else {
+              b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
             }
           }
         }
-      };
-      if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c, bc);
-      for (int s0 = 0; s0 < nsteps; s0 += PF) {
-        if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
+      }
+    };
+    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c, bc);
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+      if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          const int i = (s0 + u) * 4 + lr;
-          const bool iin = i < k;
-          const double* wr = wl + (iin ? i : 0) * LD + lc;
+      for (int u = 0; u < PF; ++u) {
+        const int i = (s0 + u) * 4 + lr;
+        const bool iin = i < k;
+        const double* wr = wl + (iin ? i : 0) * LD + lc;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) {
-            const double x = WLDS ? sel_load<PREC>(wr, n * 16, iin, n * 16) : bc[u % PB][n];
-            const BFrag<PREC> b = make_b<PREC>(x, bsc[n]);
-            acc[0][n].step(a0c[u], b);
-            if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
-          }
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) {
-            acc[0][n].flush_step();
-            acc[1][n].flush_step();
-          }
+        for (int n = 0; n < NTL; ++n) {
+          const double x = WLDS ? sel_load<PREC>(wr, n * 16, iin, n * 16) : bc[u % PB][n];
+          const BFrag<PREC> b = make_b<PREC>(x, bsc[n]);
+          acc[0][n].step(a0c[u], b);
+          if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
         }
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          acc[0][n].flush();
-          acc[1][n].flush();
-        }
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          a0c[u] = a0n[u];
-          a1c[u] = a1n[u];
-        }
-        if (!WLDS) {
-#pragma unroll
-          for (int u = 0; u < PB; ++u)
-#pragma unroll
-            for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
+          acc[0][n].flush_step();
+          acc[1][n].flush_step();
         }
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int n = 0; n < NTL; ++n) {
+        acc[0][n].flush();
+        acc[1][n].flush();
+      }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = (mt0 + u) * 16 + drow<PREC>(v, lr);
-          if (j < nr) {
-            double* dst = acc_l + static_cast<int>(red[j]) * LD + lc;
+      for (int u = 0; u < PF; ++u) {
+        a0c[u] = a0n[u];
+        a1c[u] = a1n[u];
+      }
+      if (!WLDS) {
 #pragma unroll
-            for (int n = 0; n < NTL; ++n) {
-              if (o == 0)
-                dst[n * 16] = acc[u][n].get(v);
-              else
-                dst[n * 16] += acc[u][n].get(v);
-            }
-          }
+        for (int u = 0; u < PB; ++u)
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = (mt0 + u) * 16 + drow<PREC>(v, lr);
+        if (j < nr) {
+          double* dst = acc_l + static_cast<int>(red[j]) * LD + lc;
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) atomicAdd(dst + n * 16, acc[u][n].get(v));
         }
       }
     }
-    // identity part: w_o at the skeleton rows (disjoint from the redundant rows above)
+  }
+  // identity part: w_o at the skeleton rows of each block
+  for (int o = 0; o < nouts; ++o) {
+    const int k = o ? k1 : k0;
+    const uint16_t* skel = ix + o * K;
     if (WLDS) {
+      const double* wl = o ? wl1 : wl0;
       for (int e = threadIdx.x; e < k * NT; e += 256) {
         const int i = e / NT, c = e % NT;
-        double* dst = acc_l + static_cast<int>(skel[i]) * LD + c;
-        if (o == 0)
-          *dst = wl[i * LD + c];
-        else
-          *dst += wl[i * LD + c];
+        atomicAdd(acc_l + static_cast<int>(skel[i]) * LD + c, wl[i * LD + c]);
       }
     } else {
+      const double* wg = o ? wg1 : wg0;
       staged<double>(
           k * NT, [&](int e) { return wg[static_cast<long long>(e / NT) * R + e % NT]; },
-          [&](int e, double val) {
-            double* dst = acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT;
-            if (o == 0)
-              *dst = val;
-            else
-              *dst += val;
-          });
+          [&](int e, double val) { atomicAdd(acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT, val); });
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (io.on() && tk.mp >= 0) {
     const PairDesc pd = pairs[tk.mp];
     for_leaf_block<NT>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0,
@@ -826,8 +821,8 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
   // LDS holds the task's K x NT input block: 32 columns while that stays within 100 KiB
-  // rows held in LDS: the input block, plus (transposed) the current output block
-  const long long rows = K + (transpose && PREC == PSPLIT ? lc.maxk : 0);
+  // rows held in LDS: the input block, plus (transposed split) both output blocks
+  const long long rows = K + (transpose && PREC == PSPLIT ? 2LL * lc.maxk : 0);
   const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
   if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
