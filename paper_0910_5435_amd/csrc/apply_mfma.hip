@@ -341,14 +341,15 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 // (k_0 + k_1 rows, cut on the fly from their own column scales), then the index lists.  FP64
 // and FP32 read w_o as B fragments straight from global memory (prefetched with the factor
 // fragments): their loops are not VALU-bound and the smaller LDS block keeps 32-column tiles.
-template <int NT, int PREC>
+// The split form does the same (WLDS = false) for size classes whose LDS block would
+// otherwise leave room for only one work-group per compute unit.
+template <int NT, int PREC, bool WLDS = PREC == PSPLIT>
 __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
                                  const double* __restrict__ win, double* __restrict__ xout, int R,
                                  const CoefIO& io, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  constexpr bool WLDS = PREC == PSPLIT;
   __shared__ double red_s[256];
   __shared__ int colsc[2][NT];
   const int K = tk.K;
@@ -370,8 +371,16 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
   }
   __syncthreads();
   if (PREC == PSPLIT) {
-    column_scales<NT>(k0, [&](int r, int c) { return wl0[r * LD + c]; }, red_s, colsc[0]);
-    if (nouts > 1) column_scales<NT>(k1, [&](int r, int c) { return wl1[r * LD + c]; }, red_s, colsc[1]);
+    if (WLDS) {
+      column_scales<NT>(k0, [&](int r, int c) { return wl0[r * LD + c]; }, red_s, colsc[0]);
+      if (nouts > 1) column_scales<NT>(k1, [&](int r, int c) { return wl1[r * LD + c]; }, red_s, colsc[1]);
+    } else {
+      column_scales<NT>(k0, [&](int r, int c) { return wg0[static_cast<long long>(r) * R + c]; }, red_s,
+                        colsc[0]);
+      if (nouts > 1)
+        column_scales<NT>(k1, [&](int r, int c) { return wg1[static_cast<long long>(r) * R + c]; }, red_s,
+                          colsc[1]);
+    }
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
@@ -508,7 +517,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
   }
 }
 
-template <int NT, int PREC>
+template <int NT, int PREC, bool WLDS = PREC == PSPLIT>
 __global__ void __launch_bounds__(256, kMinBlocks)
 k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
                    const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
@@ -517,7 +526,7 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  level_trans_body<NT, PREC>(tasks[ti], blk, fp, idx, pairs, win, xout, R, io, lds);
+  level_trans_body<NT, PREC, WLDS>(tasks[ti], blk, fp, idx, pairs, win, xout, R, io, lds);
 }
 
 // ------------------------------------------------------------------- final, synthesis
@@ -798,13 +807,25 @@ __global__ void k_split_rows(const double* __restrict__ src, float2* __restrict_
 }
 
 // LDS budget (bytes) under which a level or final launch takes 32-column tiles instead of 16:
-// a larger tile halves the factor reads per task but its LDS block limits how many
-// work-groups share a compute unit.  SHT_TILE32_LDS_KB overrides it (tuning).
+// a larger tile halves the factor reads per task, but only while two work-groups still fit
+// in a compute unit's 160 KiB of LDS (a 16-column tile at two work-groups per CU measured
+// faster than a 32-column tile at one).  SHT_TILE32_LDS_KB overrides it (tuning).
 long long tile32_lds_budget() {
   static const long long v = [] {
     const char* e = std::getenv("SHT_TILE32_LDS_KB");
-    const long long kb = e ? std::atoll(e) : 100;
-    return (kb > 0 ? kb : 100) * 1024;
+    const long long kb = e ? std::atoll(e) : 76;
+    return (kb > 0 ? kb : 76) * 1024;
+  }();
+  return v;
+}
+
+// Largest LDS block (bytes) for which the transposed split levels stage their output vectors
+// in LDS (two work-groups per compute unit); SHT_SPLIT_WLDS_KB overrides it (tuning).
+long long split_wlds_cap() {
+  static const long long v = [] {
+    const char* e = std::getenv("SHT_SPLIT_WLDS_KB");
+    const long long kb = e ? std::atoll(e) : 76;
+    return (kb > 0 ? kb : 76) * 1024;
   }();
   return v;
 }
@@ -820,9 +841,17 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   if (cnt == 0) return hipSuccess;
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
-  // LDS holds the task's K x NT input block: 32 columns while that stays within 100 KiB
-  // rows held in LDS: the input block, plus (transposed split) both output blocks
-  const long long rows = K + (transpose && PREC == PSPLIT ? 2LL * lc.maxk : 0);
+  // LDS holds the task's K x NT input block: 32 columns while that stays within the tile
+  // budget.  The transposed split form also stages both output blocks, unless that block
+  // would exceed split_wlds_cap() (then the vectors are read from global memory).
+  bool wlds = false;
+  long long rows = K;
+  if (transpose && PREC == PSPLIT) {
+    const long long rw = K + 2LL * lc.maxk;
+    const int ntw = (R % 32 == 0 && rw * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
+    wlds = rw * (ntw + 2) * 8 + 4LL * K + 16 <= split_wlds_cap();
+    if (wlds) rows = rw;
+  }
   const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
   if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
@@ -841,6 +870,11 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
       LEVEL_LAUNCH((k_level_synth_mfma<32, PREC>));
     else
       LEVEL_LAUNCH((k_level_synth_mfma<16, PREC>));
+  } else if (PREC == PSPLIT && !wlds) {
+    if (NT == 32)
+      LEVEL_LAUNCH((k_level_trans_mfma<32, PREC, false>));
+    else
+      LEVEL_LAUNCH((k_level_trans_mfma<16, PREC, false>));
   } else {
     if (NT == 32)
       LEVEL_LAUNCH((k_level_trans_mfma<32, PREC>));
