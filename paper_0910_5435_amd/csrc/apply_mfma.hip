@@ -120,6 +120,31 @@ __device__ __forceinline__ BFrag<PSPLIT> make_b<PSPLIT>(double x, int sh) {
 template <>
 __device__ __forceinline__ BFrag<P32> make_b<P32>(double x, int) { return {static_cast<float>(x)}; }
 
+// Split form, for vector blocks that serve only as B operands: cut the rows x NT block (row
+// stride LD) once per work-group, in place, into (x1, x2) float pairs on the column grids
+// sh[c] (each double slot then holds one float2), instead of once per row tile in every wave.
+template <int NT, int LD>
+__device__ void cut_block(double* blk, int rows, const int* sh) {
+  for (int e = threadIdx.x; e < rows * NT; e += 256) {
+    const int r = e / NT, c = e % NT;
+    double* q = blk + r * LD + c;
+    const BFrag<PSPLIT> b = make_b<PSPLIT>(*q, sh[c]);
+    *reinterpret_cast<float2*>(q) = make_float2(b.b1, b.b2);
+  }
+}
+
+// B fragment of entry p[i] (0 where ok is false) from a block prepared for PREC: FP64 and
+// FP32 values are converted here, the split form reads the pair left by cut_block.
+template <int PREC>
+__device__ __forceinline__ BFrag<PREC> b_from(const double* p, int i, bool ok, int sh) {
+  if constexpr (PREC == PSPLIT) {
+    const float2 v = ok ? *reinterpret_cast<const float2*>(p + i) : make_float2(0.0f, 0.0f);
+    return {v.x, v.y};
+  } else {
+    return make_b<PREC>(sel_load<PREC>(p, i, ok, i), sh);
+  }
+}
+
 template <int PREC> struct Acc;
 template <>
 struct Acc<P64> {
@@ -551,6 +576,9 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
   if (PREC == PSPLIT) {
     column_scales<NT>(k0, [&](int r, int c) { return w0[r * LD + c]; }, red_s, colsc[0]);
     column_scales<NT>(k1, [&](int r, int c) { return w1[r * LD + c]; }, red_s, colsc[1]);
+    cut_block<NT, LD>(w0, k0, colsc[0]);
+    cut_block<NT, LD>(w1, k1, colsc[1]);
+    __syncthreads();
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
@@ -599,12 +627,12 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc;
         if (!odd) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], make_b<PREC>(sel_load<PREC>(wr, n * 16, ain, n * 16), bsc[0][n]));
+          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], b_from<PREC>(wr, n * 16, ain, bsc[0][n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) E[n].flush_step();
         } else {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], make_b<PREC>(sel_load<PREC>(wr, n * 16, ain, n * 16), bsc[1][n]));
+          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], b_from<PREC>(wr, n * 16, ain, bsc[1][n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) O[n].flush_step();
         }
@@ -699,6 +727,9 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
     if (PREC == PSPLIT) {
       column_scales<NT>(ih, [&](int r, int c) { return eo[0][r * LD + c]; }, red_s, colsc[0]);
       column_scales<NT>(ih, [&](int r, int c) { return eo[1][r * LD + c]; }, red_s, colsc[1]);
+      cut_block<NT, LD>(eo[0], ih, colsc[0]);
+      cut_block<NT, LD>(eo[1], ih, colsc[1]);
+      __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
@@ -731,7 +762,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
           const bool iin = i < ih;
           const double* er = src + (iin ? i : 0) * LD + lc;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], make_b<PREC>(sel_load<PREC>(er, n * 16, iin, n * 16), bsc[n]));
+          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], b_from<PREC>(er, n * 16, iin, bsc[n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) acc[u][n].flush_step();
         }

@@ -173,6 +173,34 @@ def test_split_precision_matches_oracle(l, C, F):
     assert e32.max() < 1e-4
 
 
+def test_full_size_on_sampled_orders():
+    # The benchmark's shape and launch configuration (l = 1024, 64 complex fields, eps 1e-12,
+    # leaf width 64: R = 256 columns, the largest size classes) in split-FP32 and FP64.  The
+    # oracle covers a sample of orders: synthesis of coefficients that vanish outside the
+    # sample (whole grids of two fields), and the sampled orders of the analysis of a seeded
+    # grid (two fields).
+    l, C, F = 1024, 64, 64
+    P = _plan(l, C, eps=1e-12)
+    sample = [0, 1, 300, 1023, 1024, 1800, 2047]
+    ms = np.abs(syn.orders_canonical(l))
+    mask = np.isin(ms, sample)
+    beta = syn.coefficients(l, F, seed=0, power=1.5)
+    beta_s = np.where(mask[None, :], beta, 0.0)
+    f_ref = oracle.synth(beta_s[:2], l, orders=sample)
+    g = syn.grid(l, F, seed=1)
+    a_ref = oracle.analyze_orders(g[:2], l, sample)[:, mask]
+    db, dg = _dev(beta_s), _dev(g)
+    for prec, tol in (("fp64", FP64_TOL), ("split32", SPLIT_TOL)):
+        f = P.synth(db, precision=prec)
+        es = _rel(f[:2].cpu().numpy(), f_ref)
+        del f
+        a = P.analyze(dg, precision=prec)
+        ea = _rel(a[:2].cpu().numpy()[:, mask], a_ref)
+        del a
+        print(f"l={l} F={F} {prec}: synth {es.max():.2e} analysis {ea.max():.2e} (orders {sample})")
+        assert es.max() < tol and ea.max() < tol
+
+
 def test_split_precision_real_fields_and_adjoint():
     l, C, F = 64, 16, 8
     P = _plan(l, C, eps=1e-12, kind="real")
