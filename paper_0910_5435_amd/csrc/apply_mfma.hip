@@ -83,7 +83,12 @@ __device__ __forceinline__ T sel_load(const T* p, long long i, bool ok, long lon
   }
 }
 
-// Factor fragment entry i, or 0 where ok is false; `safe` is an entry of the same block.
+// Factor fragment entry i where ok holds.  Split and FP32: where it does not, the entry at
+// `safe` (the block's first) is loaded instead and used as it is: such a fragment either
+// meets zero B entries (past the end of the contraction) or feeds output rows that are
+// never stored, and every stored factor is finite, so it contributes nothing.  Loading
+// unconditionally and not touching the value until the MFMA keeps the prefetched loads in
+// flight.  FP64 skips the masked loads and substitutes 0, which measured slightly faster.
 template <int PREC>
 __device__ __forceinline__ AFrag<PREC> load_a(const FacPtr& f, long long i, bool ok, long long safe);
 template <>
@@ -91,14 +96,14 @@ __device__ __forceinline__ AFrag<P64> load_a<P64>(const FacPtr& f, long long i, 
   return {ok ? f.d[i] : 0.0};
 }
 template <>
-__device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok, long long) {
-  const float2 v = ok ? f.hl[i] : make_float2(0.0f, 0.0f);
+__device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long long i, bool ok, long long safe) {
+  const float2 v = f.hl[ok ? i : safe];
   return {v.x, v.y};
 }
 template <>
 __device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok, long long safe) {
   const float2 v = f.hl[ok ? i : safe];
-  return {ok ? v.x + v.y : 0.0f};
+  return {v.x + v.y};
 }
 
 template <int PREC> struct BFrag;
@@ -281,11 +286,14 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
       }
     }
     const int i0 = mt0 * 16 + lc, i1 = i0 + 16;
-    // factor fragments are fetched PF K-steps ahead (double-buffered in registers)
+    // factor fragments are fetched PF K-steps ahead (double-buffered in registers), and with
+    // them the LDS row offsets of the gathered vector rows, so that a K-step waits on one LDS
+    // read instead of two dependent ones
     constexpr int PF = kPrefetch;
     const int nsteps = (nr + 3) >> 2;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
-    auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1) {
+    int roc[PF], ron[PF];
+    auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, int* ro) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
@@ -293,18 +301,18 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const long long base = toff + static_cast<long long>(kk) * k;
         d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k, toff);
         d1[u] = load_a<PREC>(fp, base + i1, kin && two && i1 < k, toff);
+        ro[u] = red[kin ? kk : 0] * LD;
       }
     };
     // the branch-free loads read the block's first entry, which exists only when there is a step
-    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c);
+    if (nsteps > 0) fetch(0, a0c, a1c, roc);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
-      if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n);
+      if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, ron);
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
         const bool kin = kk < nr;
-        const int rr = kBranchFree<PREC> ? red[kin ? kk : 0] : (kin ? red[kk] : 0);
-        const double* xr = xs + rr * LD + lc;
+        const double* xr = xs + roc[u] + lc;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           const BFrag<PREC> b = make_b<PREC>(sel_load<PREC>(xr, n * 16, kin, n * 16), bsc[n]);
@@ -327,6 +335,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int u = 0; u < PF; ++u) {
         a0c[u] = a0n[u];
         a1c[u] = a1n[u];
+        roc[u] = ron[u];
       }
     }
     double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
@@ -457,7 +466,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         }
       }
     };
-    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, a0c, a1c, bc);
+    if (nsteps > 0) fetch(0, a0c, a1c, bc);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
 #pragma unroll
@@ -614,7 +623,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin, safe);
       }
     };
-    if (!kBranchFree<PREC> || nsteps > 0) fetch(0, ac);
+    if (nsteps > 0) fetch(0, ac);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
       if (s0 + PF < nsteps) fetch(s0 + PF, an);
 #pragma unroll
@@ -753,7 +762,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
           d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k, soff);
         }
       };
-      if (!kBranchFree<PREC> || nsteps > 0) fetch(0, ac);
+      if (nsteps > 0) fetch(0, ac);
       for (int s0 = 0; s0 < nsteps; s0 += PF) {
         if (s0 + PF < nsteps) fetch(s0 + PF, an);
 #pragma unroll
@@ -883,7 +892,10 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
     wlds = rw * (ntw + 2) * 8 + 4LL * K + 16 <= split_wlds_cap();
     if (wlds) rows = rw;
   }
-  const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
+  // (the split kernel without staging takes 16-column tiles: at 32 it runs out of registers)
+  const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget() && !(transpose && PREC == PSPLIT && !wlds))
+                     ? 32
+                     : 16;
   if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
@@ -902,10 +914,7 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
     else
       LEVEL_LAUNCH((k_level_synth_mfma<16, PREC>));
   } else if (PREC == PSPLIT && !wlds) {
-    if (NT == 32)
-      LEVEL_LAUNCH((k_level_trans_mfma<32, PREC, false>));
-    else
-      LEVEL_LAUNCH((k_level_trans_mfma<16, PREC, false>));
+    LEVEL_LAUNCH((k_level_trans_mfma<16, PREC, false>));
   } else {
     if (NT == 32)
       LEVEL_LAUNCH((k_level_trans_mfma<32, PREC>));
@@ -999,7 +1008,10 @@ __device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* ld
     if (it.kind == kItemLevel) {
       const double* in = t % 2 ? g.v1 : g.v0;
       double* out = t == 0 ? nullptr : ((t - 1) % 2 ? g.v1 : g.v0);
-      level_trans_body<NT, PREC>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io, lds);
+      // the split vectors are read from global memory here: staging them would size every
+      // work-group's LDS for the largest pair of output blocks of any group
+      level_trans_body<NT, PREC, false>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io,
+                                        lds);
     } else {  // transposed finals always take 16-column blocks
       final_trans_body<16, 128, PREC>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0, g.v1,
                                       g.l, g.R, lds);

@@ -114,11 +114,10 @@ void free_batch(sht_batch_s* B) {
 
 // Largest input length of any level task and dynamic LDS of one item of a group.
 size_t group_lds(const sht_plan_s* P, int nt, bool trans, int precision) {
-  int maxK = 0, maxk = 0;
+  int maxK = 0;
   for (int v : P->step_maxK) maxK = std::max(maxK, v);
-  for (int v : P->step_maxk) maxk = std::max(maxk, v);
-  // transposed level items of the split form also hold both output blocks
-  const size_t rows = static_cast<size_t>(maxK) + (trans && precision == SHT_SPLIT32 ? 2 * maxk : 0);
+  (void)precision;  // transposed level items read their output vectors from global memory
+  const size_t rows = static_cast<size_t>(maxK);
   size_t lds = rows * (nt + 2) * 8 + 4 * static_cast<size_t>(maxK) + 16;
   if (trans)
     lds = std::max(lds, final_trans_lds_bytes());
