@@ -29,7 +29,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double wr, double wi) {
   return make_double2(a.x * wr - a.y * wi, a.x * wi + a.y * wr);
 }
 
-// In-place DIT on bit-reversed input; sign +1 uses e^{+i}, -1 uses e^{-i}.
+// In-place DIT on a bit-reversed row; sign +1 uses e^{+i}, -1 uses e^{-i}.
 __device__ void fft_lds(double2* X, int N, int logN, const double* __restrict__ tw, double sign) {
   int s = 0;
   for (; s + 1 < logN; s += 2) {
@@ -41,17 +41,17 @@ __device__ void fft_lds(double2* X, int N, int logN, const double* __restrict__ 
       // stage s: pairs (i0, i0+h), (i0+2h, i0+3h), twiddle e^{i pi pos / h}
       const int q1 = pos * (N >> (s + 1));
       const double w1r = tw[2 * q1], w1i = sign * tw[2 * q1 + 1];
-      const double2 x0 = X[i0], x1 = cmul(X[i0 + h], w1r, w1i);
-      const double2 x2 = X[i0 + 2 * h], x3 = cmul(X[i0 + 3 * h], w1r, w1i);
-      double2 a0 = make_double2(x0.x + x1.x, x0.y + x1.y);
-      double2 a1 = make_double2(x0.x - x1.x, x0.y - x1.y);
-      double2 a2 = make_double2(x2.x + x3.x, x2.y + x3.y);
-      double2 a3 = make_double2(x2.x - x3.x, x2.y - x3.y);
       // stage s+1: pairs (i0, i0+2h) with e^{i pi pos/(2h)}, (i0+h, i0+3h) with e^{i pi (pos+h)/(2h)}
       const int q2 = pos * (N >> (s + 2));
       const int q3 = (pos + h) * (N >> (s + 2));
-      a2 = cmul(a2, tw[2 * q2], sign * tw[2 * q2 + 1]);
-      a3 = cmul(a3, tw[2 * q3], sign * tw[2 * q3 + 1]);
+      const double w2r = tw[2 * q2], w2i = sign * tw[2 * q2 + 1];
+      const double w3r = tw[2 * q3], w3i = sign * tw[2 * q3 + 1];
+      const double2 x0 = X[i0], x1 = cmul(X[i0 + h], w1r, w1i);
+      const double2 x2 = X[i0 + 2 * h], x3 = cmul(X[i0 + 3 * h], w1r, w1i);
+      const double2 a0 = make_double2(x0.x + x1.x, x0.y + x1.y);
+      const double2 a1 = make_double2(x0.x - x1.x, x0.y - x1.y);
+      const double2 a2 = cmul(make_double2(x2.x + x3.x, x2.y + x3.y), w2r, w2i);
+      const double2 a3 = cmul(make_double2(x2.x - x3.x, x2.y - x3.y), w3r, w3i);
       X[i0] = make_double2(a0.x + a2.x, a0.y + a2.y);
       X[i0 + 2 * h] = make_double2(a0.x - a2.x, a0.y - a2.y);
       X[i0 + h] = make_double2(a1.x + a3.x, a1.y + a3.y);
@@ -65,7 +65,8 @@ __device__ void fft_lds(double2* X, int N, int logN, const double* __restrict__ 
       const int pos = b & (h - 1);
       const int i0 = ((b >> s) << (s + 1)) + pos;
       const int q = pos * (N >> (s + 1));
-      const double2 a = X[i0], c = cmul(X[i0 + h], tw[2 * q], sign * tw[2 * q + 1]);
+      const double wr = tw[2 * q], wi = sign * tw[2 * q + 1];
+      const double2 a = X[i0], c = cmul(X[i0 + h], wr, wi);
       X[i0] = make_double2(a.x + c.x, a.y + c.y);
       X[i0 + h] = make_double2(a.x - c.x, a.y - c.y);
     }
@@ -93,6 +94,8 @@ __device__ __forceinline__ double* field_grid(double* grid, double* const* fptr,
   return grid + static_cast<long long>(f) * (2LL * l) * (4LL * l) * (kind == SHT_COMPLEX ? 2 : 1);
 }
 
+// One thread per order m: the bins +m and -m of the field sit next to each other in the Y
+// row (m, ring), so they are read together.
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* const* __restrict__ fptr,
             const double* __restrict__ tw, int l, int R, int F, int kind) {
@@ -102,34 +105,33 @@ k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* con
   if (!ring_field(L2, F, ring, f)) return;
   const int N = 4 * l;
   const int logN = 31 - __clz(N);
-  // gathers in batches of kBatch per thread, all issued before the LDS stores
-  for (int b0 = threadIdx.x; b0 < N; b0 += kFftThreads * kBatch) {
-    double2 v[kBatch];
+  const int w = kind == SHT_COMPLEX ? 4 : 2;  // Y words per field
+  // m = 0 .. 2l-1; the bin 2l (order 2l is outside the band) is zero
+  for (int m0 = threadIdx.x; m0 < L2; m0 += kFftThreads * kBatch) {
+    double2 v[kBatch][2];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int b = b0 + u * kFftThreads;
-      v[u] = make_double2(0.0, 0.0);
-      if (b < L2) {
-        const long long row = static_cast<long long>(b) * L2 + ring;
-        const double* src = Y + row * R + (kind == SHT_COMPLEX ? 4 * f : 2 * f);
-        v[u] = *reinterpret_cast<const double2*>(src);
-      } else if (b > L2 && b < N) {
-        const int m = N - b;
-        const long long row = static_cast<long long>(m) * L2 + ring;
-        if (kind == SHT_COMPLEX) {
-          v[u] = *reinterpret_cast<const double2*>(Y + row * R + 4 * f + 2);
-        } else {
-          const double2 g = *reinterpret_cast<const double2*>(Y + row * R + 2 * f);
-          v[u] = make_double2(g.x, -g.y);  // g_{-m} = conj(g_m) for real fields
-        }
+      const int m = m0 + u * kFftThreads;
+      v[u][0] = v[u][1] = make_double2(0.0, 0.0);
+      if (m < L2) {
+        const double* src = Y + (static_cast<long long>(m) * L2 + ring) * R + w * f;
+        v[u][0] = *reinterpret_cast<const double2*>(src);
+        if (kind == SHT_COMPLEX)
+          v[u][1] = *reinterpret_cast<const double2*>(src + 2);
+        else
+          v[u][1] = make_double2(v[u][0].x, -v[u][0].y);  // g_{-m} = conj(g_m) for real fields
       }
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int b = b0 + u * kFftThreads;
-      if (b < N) X[bitrev(b, logN)] = v[u];
+      const int m = m0 + u * kFftThreads;
+      if (m < L2) {
+        X[bitrev(m, logN)] = v[u][0];
+        if (m > 0) X[bitrev(N - m, logN)] = v[u][1];
+      }
     }
   }
+  if (threadIdx.x == 0) X[bitrev(L2, logN)] = make_double2(0.0, 0.0);
   fft_lds(X, N, logN, tw, 1.0);
   double* gb = field_grid(grid, fptr, f, l, kind);
   const long long rowbase = static_cast<long long>(ring) * N;
