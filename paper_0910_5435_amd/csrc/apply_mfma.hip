@@ -24,7 +24,9 @@
 //
 // Register layouts (checked on gfx950): for both 16x16x4 shapes A[i][k] sits in lane
 // i + 16k and B[k][j] in lane j + 16k; the FP64 result D[4v + lane/16][lane%16] is in
-// element v, the FP32 result D[4(lane/16) + v][lane%16].
+// element v, the FP32 result D[4(lane/16) + v][lane%16].  With NT = 16 NTL columns per work-group, column
+// tile n of a lane with lane%16 = c is work-group column c NTL + n: a lane's columns are
+// adjacent, so its B entries and results of one row move as one 16-byte access.
 #include <algorithm>
 #include <cstdlib>
 
@@ -150,6 +152,39 @@ __device__ __forceinline__ BFrag<PREC> b_from(const double* p, int i, bool ok, i
   }
 }
 
+// The NTL adjacent entries p[0 .. NTL) of a lane's columns (zeros where ok is false): one
+// 16-byte load for two (p is 16-byte aligned), except in the branch-free FP32 form, where
+// separate loads measured faster; p is readable when ok is false in that form.
+template <int NTL, int PREC>
+__device__ __forceinline__ void load_cols(const double* p, bool ok, double (&x)[NTL]) {
+  if constexpr (NTL == 2 && !kBranchFree<PREC>) {
+    const double2 v = ok ? *reinterpret_cast<const double2*>(p) : make_double2(0.0, 0.0);
+    x[0] = v.x;
+    x[1] = v.y;
+  } else {
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) x[n] = sel_load<PREC>(p, n, ok, n);
+  }
+}
+
+// B fragments of a lane's NTL columns from a block prepared for PREC (see b_from).
+template <int NTL, int PREC>
+__device__ __forceinline__ void b_cols(const double* p, bool ok, const int (&sh)[NTL], BFrag<PREC> (&b)[NTL]) {
+  if constexpr (PREC == PSPLIT && NTL == 2) {
+    const float4 v = ok ? *reinterpret_cast<const float4*>(p) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    b[0] = {v.x, v.y};
+    b[1] = {v.z, v.w};
+  } else if constexpr (PREC == PSPLIT) {
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) b[n] = b_from<PREC>(p, n, ok, sh[n]);
+  } else {
+    double x[NTL];
+    load_cols<NTL, PREC>(p, ok, x);
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) b[n] = make_b<PREC>(x[n], sh[n]);
+  }
+}
+
 template <int PREC> struct Acc;
 template <>
 struct Acc<P64> {
@@ -260,7 +295,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
   const int lc = lane & 15, lr = lane >> 4;
   int bsc[NTL];
 #pragma unroll
-  for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[n * 16 + lc] : 0;
+  for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[lc * NTL + n] : 0;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
   const int np0 = (nm0 + 1) >> 1, np1 = (nm1 + 1) >> 1;  // pairs of row tiles per output
   for (int q = wave; q < np0 + np1; q += 4) {
@@ -281,7 +316,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
-          acc[u][n].set(v, row < k ? xs[skel[row] * LD + n * 16 + lc] : 0.0);
+          acc[u][n].set(v, row < k ? xs[skel[row] * LD + lc * NTL + n] : 0.0);
         }
       }
     }
@@ -312,10 +347,11 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
         const bool kin = kk < nr;
-        const double* xr = xs + roc[u] + lc;
+        double xv[NTL];
+        load_cols<NTL, PREC>(xs + roc[u] + lc * NTL, kin, xv);
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          const BFrag<PREC> b = make_b<PREC>(sel_load<PREC>(xr, n * 16, kin, n * 16), bsc[n]);
+          const BFrag<PREC> b = make_b<PREC>(xv[n], bsc[n]);
           acc[0][n].step(a0c[u], b);
           // acc[1] sees zero fragments when !two; the branch-free form runs it anyway
           if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
@@ -338,7 +374,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         roc[u] = ron[u];
       }
     }
-    double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc;
+    double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc * NTL;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
@@ -346,7 +382,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
         if (row < k) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n * 16] = acc[u][n].get(v);
+          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n] = acc[u][n].get(v);
         }
       }
     }
@@ -433,7 +469,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
     const double* wl = o ? wl1 : wl0;
     int bsc[NTL];
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[o][n * 16 + lc] : 0;
+    for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[o][lc * NTL + n] : 0;
     Acc<PREC> acc[2][NTL];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -453,17 +489,9 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const long long base = toff + static_cast<long long>(i) * nr;
         d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr, toff);
         d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr, toff);
-        if (!WLDS) {
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) {
-            if constexpr (kBranchFree<PREC>) {  // row 0 stands in for rows past the block
-              const double wv = wg[static_cast<long long>(iin ? i : 0) * R + n * 16 + lc];
-              b[u % PB][n] = iin ? wv : 0.0;
-            } else {
-              b[u % PB][n] = iin ? wg[static_cast<long long>(i) * R + n * 16 + lc] : 0.0;
-            }
-          }
-        }
+        if (!WLDS)  // (branch-free: row 0 stands in for rows past the block)
+          load_cols<NTL, PREC>(wg + static_cast<long long>(kBranchFree<PREC> && !iin ? 0 : i) * R + lc * NTL, iin,
+                               b[u % PB]);
       }
     };
     if (nsteps > 0) fetch(0, a0c, a1c, bc);
@@ -473,11 +501,11 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int u = 0; u < PF; ++u) {
         const int i = (s0 + u) * 4 + lr;
         const bool iin = i < k;
-        const double* wr = wl + (iin ? i : 0) * LD + lc;
+        double xv[NTL];
+        if (WLDS) load_cols<NTL, PREC>(wl + (iin ? i : 0) * LD + lc * NTL, iin, xv);
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          const double x = WLDS ? sel_load<PREC>(wr, n * 16, iin, n * 16) : bc[u % PB][n];
-          const BFrag<PREC> b = make_b<PREC>(x, bsc[n]);
+          const BFrag<PREC> b = make_b<PREC>(WLDS ? xv[n] : bc[u % PB][n], bsc[n]);
           acc[0][n].step(a0c[u], b);
           if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
         }
@@ -510,9 +538,9 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int v = 0; v < 4; ++v) {
         const int j = (mt0 + u) * 16 + drow<PREC>(v, lr);
         if (j < nr) {
-          double* dst = acc_l + static_cast<int>(red[j]) * LD + lc;
+          double* dst = acc_l + static_cast<int>(red[j]) * LD + lc * NTL;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) atomicAdd(dst + n * 16, acc[u][n].get(v));
+          for (int n = 0; n < NTL; ++n) atomicAdd(dst + n, acc[u][n].get(v));
         }
       }
     }
@@ -596,7 +624,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) bsc[p][n] = PREC == PSPLIT ? colsc[p][n * 16 + lc] : 0;
+    for (int n = 0; n < NTL; ++n) bsc[p][n] = PREC == PSPLIT ? colsc[p][lc * NTL + n] : 0;
   const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   const int nm = (h + 15) >> 4;
   for (int mt = wave; mt < nm; mt += 4) {
@@ -633,15 +661,23 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         const bool odd = st >= n0;
         const int a = (odd ? st - n0 : st) * 4 + lr;
         const bool ain = a < (odd ? k1 : k0);
-        const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc;
+        const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc * NTL;
         if (!odd) {
+          {
+            BFrag<PREC> b[NTL];
+            b_cols<NTL, PREC>(wr, ain, bsc[0], b);
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) E[n].step(ac[u], b_from<PREC>(wr, n * 16, ain, bsc[0][n]));
+            for (int n = 0; n < NTL; ++n) E[n].step(ac[u], b[n]);
+          }
 #pragma unroll
           for (int n = 0; n < NTL; ++n) E[n].flush_step();
         } else {
+          {
+            BFrag<PREC> b[NTL];
+            b_cols<NTL, PREC>(wr, ain, bsc[1], b);
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) O[n].step(ac[u], b_from<PREC>(wr, n * 16, ain, bsc[1][n]));
+            for (int n = 0; n < NTL; ++n) O[n].step(ac[u], b[n]);
+          }
 #pragma unroll
           for (int n = 0; n < NTL; ++n) O[n].flush_step();
         }
@@ -660,13 +696,13 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
       if (ii < h) {
         const int row = ft.row0 + ii;
         const double s = invD[row];
-        double* yp = Y + (ybase + l + row) * R + c0 + lc;
-        double* ym = Y + (ybase + l - 1 - row) * R + c0 + lc;
+        double* yp = Y + (ybase + l + row) * R + c0 + lc * NTL;
+        double* ym = Y + (ybase + l - 1 - row) * R + c0 + lc * NTL;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           const double e = E[n].get(v), od = O[n].get(v);
-          yp[n * 16] = (e + od) * s;
-          ym[n * 16] = (e - od) * s;
+          yp[n] = (e + od) * s;
+          ym[n] = (e - od) * s;
         }
       }
     }
@@ -751,7 +787,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       const double* src = eo[p];
       int bsc[NTL];
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[p][n * 16 + lc] : 0;
+      for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[p][lc * NTL + n] : 0;
       constexpr int PF = kPrefetch;
       const int nsteps = (ih + 3) >> 2;
       AFrag<PREC> ac[PF], an[PF];
@@ -769,9 +805,9 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
           const bool iin = i < ih;
-          const double* er = src + (iin ? i : 0) * LD + lc;
+          const double* er = src + (iin ? i : 0) * LD + lc * NTL;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], b_from<PREC>(er, n * 16, iin, bsc[n]));
+          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], b_from<PREC>(er, n, iin, bsc[n]));
 #pragma unroll
           for (int n = 0; n < NTL; ++n) acc[u][n].flush_step();
         }
@@ -789,13 +825,13 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
     const int p = q < nm0 ? 0 : 1;
     const int k = p ? k1 : k0;
     const int mt = p ? q - nm0 : q;
-    double* vout = V + static_cast<long long>(ft.in_row[p]) * R + c0 + lc;
+    double* vout = V + static_cast<long long>(ft.in_row[p]) * R + c0 + lc * NTL;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = mt * 16 + drow<PREC>(v, lr);
       if (a < k) {
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) vout[static_cast<long long>(a) * R + n * 16] = acc[u][n].get(v);
+        for (int n = 0; n < NTL; ++n) vout[static_cast<long long>(a) * R + n] = acc[u][n].get(v);
       }
     }
   }
