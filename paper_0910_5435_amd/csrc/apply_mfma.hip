@@ -65,7 +65,7 @@ __device__ __forceinline__ int drow(int v, int lr) { return PREC == P64 ? 4 * v 
 template <int PREC> struct AFrag;
 template <> struct AFrag<P64> { double a; };
 template <> struct AFrag<PSPLIT> { float a1, a2; };
-template <> struct AFrag<P32> { float a; };
+template <> struct AFrag<P32> { float a1, a2; };  // summed at the MFMA, after the load lands
 
 // FP32 fragment loads are branch-free: the load always happens (from `safe`, an entry of the
 // same block, where ok is false) and the zero is selected afterwards, because a per-lane
@@ -105,7 +105,7 @@ __device__ __forceinline__ AFrag<PSPLIT> load_a<PSPLIT>(const FacPtr& f, long lo
 template <>
 __device__ __forceinline__ AFrag<P32> load_a<P32>(const FacPtr& f, long long i, bool ok, long long safe) {
   const float2 v = f.hl[ok ? i : safe];
-  return {v.x + v.y};
+  return {v.x, v.y};
 }
 
 template <int PREC> struct BFrag;
@@ -234,7 +234,7 @@ struct Acc<P32> {
     v = f4{0.f, 0.f, 0.f, 0.f};
   }
   __device__ void set(int e, double x) { base[e] = x; }
-  __device__ void step(const AFrag<P32>& a, const BFrag<P32>& b) { v = mfma32(a.a, b.b, v); }
+  __device__ void step(const AFrag<P32>& a, const BFrag<P32>& b) { v = mfma32(a.a1 + a.a2, b.b, v); }
   __device__ void flush_step() {}
   __device__ void flush() {}
   __device__ double get(int e) const { return base[e] + static_cast<double>(v[e]); }
@@ -339,10 +339,20 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         ro[u] = red[kin ? kk : 0] * LD;
       }
     };
-    // the branch-free loads read the block's first entry, which exists only when there is a step
-    if (nsteps > 0) fetch(0, a0c, a1c, roc);
+    // Each block's fragments are taken over at the top of the loop (the only wait on their
+    // loads, issued one block earlier), then the next block's loads are issued; the
+    // scheduling barrier keeps the compiler from sinking them towards their use.  The
+    // unmasked loads read the block's first entry, which exists only when there is a step.
+    if (nsteps > 0) fetch(0, a0n, a1n, ron);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        a0c[u] = a0n[u];
+        a1c[u] = a1n[u];
+        roc[u] = ron[u];
+      }
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, ron);
+      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
@@ -366,12 +376,6 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int n = 0; n < NTL; ++n) {
         acc[0][n].flush();
         acc[1][n].flush();
-      }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        a0c[u] = a0n[u];
-        a1c[u] = a1n[u];
-        roc[u] = ron[u];
       }
     }
     double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc * NTL;
@@ -494,9 +498,21 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                b[u % PB]);
       }
     };
-    if (nsteps > 0) fetch(0, a0c, a1c, bc);
-    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+    if (nsteps > 0) fetch(0, a0n, a1n, bn);
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the synthesis loop)
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        a0c[u] = a0n[u];
+        a1c[u] = a1n[u];
+      }
+      if (!WLDS) {
+#pragma unroll
+        for (int u = 0; u < PB; ++u)
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
+      }
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
+      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int i = (s0 + u) * 4 + lr;
@@ -519,17 +535,6 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
       for (int n = 0; n < NTL; ++n) {
         acc[0][n].flush();
         acc[1][n].flush();
-      }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        a0c[u] = a0n[u];
-        a1c[u] = a1n[u];
-      }
-      if (!WLDS) {
-#pragma unroll
-        for (int u = 0; u < PB; ++u)
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
       }
     }
 #pragma unroll
@@ -651,9 +656,12 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin, safe);
       }
     };
-    if (nsteps > 0) fetch(0, ac);
-    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+    if (nsteps > 0) fetch(0, an);
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
+#pragma unroll
+      for (int u = 0; u < PF; ++u) ac[u] = an[u];
       if (s0 + PF < nsteps) fetch(s0 + PF, an);
+      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int st = s0 + u;
@@ -687,8 +695,6 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         E[n].flush();
         O[n].flush();
       }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) ac[u] = an[u];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -798,9 +804,12 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
           d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k, soff);
         }
       };
-      if (nsteps > 0) fetch(0, ac);
-      for (int s0 = 0; s0 < nsteps; s0 += PF) {
+      if (nsteps > 0) fetch(0, an);
+      for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
+#pragma unroll
+        for (int w = 0; w < PF; ++w) ac[w] = an[w];
         if (s0 + PF < nsteps) fetch(s0 + PF, an);
+        __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
@@ -813,8 +822,6 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
         }
 #pragma unroll
         for (int n = 0; n < NTL; ++n) acc[u][n].flush();
-#pragma unroll
-        for (int w = 0; w < PF; ++w) ac[w] = an[w];
       }
     }
   }
