@@ -263,7 +263,7 @@ __device__ void column_scales(int rows, Fetch&& fetch, double* red, int* sc) {
 // ------------------------------------------------------------------- level, synthesis
 // One (task, column block): out_o = in[skel_o] + T_o in[red_o] for the task's outputs.  The
 // input block is staged in `lds` (K x (NT + 2) doubles, then the index lists).
-template <int NT, int PREC>
+template <int NT, int PREC, bool PIN = true>
 __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
                                  const double* __restrict__ in, double* __restrict__ out, int R,
@@ -341,8 +341,10 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
     };
     // Each block's fragments are taken over at the top of the loop (the only wait on their
     // loads, issued one block earlier), then the next block's loads are issued; the
-    // scheduling barrier keeps the compiler from sinking them towards their use.  The
-    // unmasked loads read the block's first entry, which exists only when there is a step.
+    // scheduling barrier (PIN) keeps the compiler from sinking them towards their use.  The
+    // persistent batch kernel leaves the placement to the compiler: there the barrier raised
+    // its register use and slowed it down.  The unmasked loads read the block's first entry,
+    // which exists only when there is a step.
     if (nsteps > 0) fetch(0, a0n, a1n, ron);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {
 #pragma unroll
@@ -352,7 +354,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         roc[u] = ron[u];
       }
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, ron);
-      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+      if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int kk = (s0 + u) * 4 + lr;
@@ -417,7 +419,7 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 // fragments): their loops are not VALU-bound and the smaller LDS block keeps 32-column tiles.
 // The split form does the same (WLDS = false) for size classes whose LDS block would
 // otherwise leave room for only one work-group per compute unit.
-template <int NT, int PREC, bool WLDS = PREC == PSPLIT>
+template <int NT, int PREC, bool WLDS = PREC == PSPLIT, bool PIN = true>
 __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
                                  const double* __restrict__ win, double* __restrict__ xout, int R,
@@ -512,7 +514,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
           for (int n = 0; n < NTL; ++n) bc[u][n] = bn[u][n];
       }
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, bn);
-      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+      if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int i = (s0 + u) * 4 + lr;
@@ -598,7 +600,7 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
 
 // ------------------------------------------------------------------- final, synthesis
 // E = S_0 v_0, O = S_1 v_1 on one 16-row tile; g(+-x) = (E +- O) / D.
-template <int NT, int PREC>
+template <int NT, int PREC, bool PIN = true>
 __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
                                  const double* __restrict__ v0buf, const double* __restrict__ v1buf,
                                  const double* __restrict__ invD, double* __restrict__ Y, int l, int R,
@@ -661,7 +663,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
 #pragma unroll
       for (int u = 0; u < PF; ++u) ac[u] = an[u];
       if (s0 + PF < nsteps) fetch(s0 + PF, an);
-      __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+      if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         const int st = s0 + u;
@@ -734,7 +736,7 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
 template <int NT, int ICH>
 constexpr size_t final_trans_lds() { return 2 * ICH * ldp<NT>() * sizeof(double); }
 
-template <int NT, int ICH, int PREC>
+template <int NT, int ICH, int PREC, bool PIN = true>
 __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
                                  const double* __restrict__ Yin, const double* __restrict__ scale,
                                  double half, double* __restrict__ v0buf, double* __restrict__ v1buf,
@@ -809,7 +811,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
 #pragma unroll
         for (int w = 0; w < PF; ++w) ac[w] = an[w];
         if (s0 + PF < nsteps) fetch(s0 + PF, an);
-        __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+        if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
@@ -1043,9 +1045,9 @@ __device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* ld
     if (it.kind == kItemLevel) {
       const double* in = t == 0 ? nullptr : ((t - 1) % 2 ? g.v1 : g.v0);
       double* out = t % 2 ? g.v1 : g.v0;
-      level_synth_body<NT, PREC>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io, lds);
+      level_synth_body<NT, PREC, false>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io, lds);
     } else {
-      final_synth_body<NT, PREC>(g.finals[it.task], it.blk, g.fp, g.v0, g.v1, g.rowscale, g.y, g.l, g.R, lds);
+      final_synth_body<NT, PREC, false>(g.finals[it.task], it.blk, g.fp, g.v0, g.v1, g.rowscale, g.y, g.l, g.R, lds);
     }
   } else {
     if (it.kind == kItemLevel) {
@@ -1053,10 +1055,10 @@ __device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* ld
       double* out = t == 0 ? nullptr : ((t - 1) % 2 ? g.v1 : g.v0);
       // the split vectors are read from global memory here: staging them would size every
       // work-group's LDS for the largest pair of output blocks of any group
-      level_trans_body<NT, PREC, false>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io,
+      level_trans_body<NT, PREC, false, false>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io,
                                         lds);
     } else {  // transposed finals always take 16-column blocks
-      final_trans_body<16, 128, PREC>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0, g.v1,
+      final_trans_body<16, 128, PREC, false>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0, g.v1,
                                       g.l, g.R, lds);
     }
   }
