@@ -11,7 +11,8 @@
 //    are summed in FP32 for one K-step and then added into the FP64 accumulator as well,
 //    which keeps their rounding near 2^-35 of the result.  Factor slices are prepared once
 //    per plan; vector slices are cut on the fly from per-task, per-column scales.
-//  * FP32: plain v_mfma_f32_16x16x4f32 on fp32(a), fp32(b), FP32 accumulation.
+//  * FP32: plain v_mfma_f32_16x16x4f32 on the FP32 sum of a factor's split pair and on
+//    fp32(b), FP32 accumulation.
 //
 // Each interpolation is a small GEMM with a gathered operand: out = in[skel] + T in[red]
 // (synthesis) or in = sum_o scatter(T_o^T w_o, w_o) (transposed).  A work-group takes one
@@ -24,9 +25,10 @@
 //
 // Register layouts (checked on gfx950): for both 16x16x4 shapes A[i][k] sits in lane
 // i + 16k and B[k][j] in lane j + 16k; the FP64 result D[4v + lane/16][lane%16] is in
-// element v, the FP32 result D[4(lane/16) + v][lane%16].  With NT = 16 NTL columns per work-group, column
-// tile n of a lane with lane%16 = c is work-group column c NTL + n: a lane's columns are
-// adjacent, so its B entries and results of one row move as one 16-byte access.
+// element v, the FP32 result D[4(lane/16) + v][lane%16].  With NT = 16 NTL columns per
+// work-group, column tile n of a lane with lane%16 = c is work-group column c NTL + n: a
+// lane's columns are adjacent, so its B entries and results of one row move as one 16-byte
+// access.
 #include <algorithm>
 #include <cstdlib>
 
