@@ -929,20 +929,19 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
   // LDS holds the task's K x NT input block: 32 columns while that stays within the tile
-  // budget.  The transposed split form also stages both output blocks, unless that block
-  // would exceed split_wlds_cap() (then the vectors are read from global memory).
+  // budget.  The split form always takes 16 columns: its 16-column kernels fit three waves
+  // per SIMD in registers, which measured faster than the halved factor reads of 32 (FP64
+  // measured the other way).  The transposed split form also stages both output blocks,
+  // unless that block would exceed split_wlds_cap() (then the vectors are read from global
+  // memory).
   bool wlds = false;
   long long rows = K;
   if (transpose && PREC == PSPLIT) {
     const long long rw = K + 2LL * lc.maxk;
-    const int ntw = (R % 32 == 0 && rw * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
-    wlds = rw * (ntw + 2) * 8 + 4LL * K + 16 <= split_wlds_cap();
+    wlds = rw * 18 * 8 + 4LL * K + 16 <= split_wlds_cap();
     if (wlds) rows = rw;
   }
-  // (the split kernel without staging takes 16-column tiles: at 32 it runs out of registers)
-  const int NT = (R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget() && !(transpose && PREC == PSPLIT && !wlds))
-                     ? 32
-                     : 16;
+  const int NT = (PREC != PSPLIT && R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
   if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
@@ -985,7 +984,8 @@ hipError_t final_launch(const sht_plan_s* P, bool transpose, const double* v0, c
       const long long cnt = lc.cnt;
       const FinalTask* tasks = P->d.finals + lc.off;
       const long long rows = 2LL * lc.maxk;
-      const int NT = (R % 32 == 0 && rows * 34 * 8 <= std::min(80LL * 1024, tile32_lds_budget())) ? 32 : 16;
+      const int NT =
+          (PREC != PSPLIT && R % 32 == 0 && rows * 34 * 8 <= std::min(80LL * 1024, tile32_lds_budget())) ? 32 : 16;
       const int nblk = R / NT;
       const dim3 grid(xcd_grid(cnt, nblk));
       const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 16;
