@@ -367,7 +367,8 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         for (int n = 0; n < NTL; ++n) {
           const BFrag<PREC> b = make_b<PREC>(xv[n], bsc[n]);
           acc[0][n].step(a0c[u], b);
-          // acc[1] sees zero fragments when !two; the branch-free form runs it anyway
+          // when !two the second tile's rows lie past the block and are never stored; the
+          // branch-free form computes it anyway
           if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
         }
 #pragma unroll
