@@ -4,6 +4,8 @@ The compute path lives in ``libsht.so`` (HIP kernels for gfx950 behind a C ABI);
 this package only binds it.  Importing the package does not load the library;
 the first call that needs it does, and raises ImportError if it was not built.
 """
-from .sht import Batch, Butterfly, Plan, coeff_index, gl_nodes, num_coeffs
+from .sht import (Batch, Butterfly, Plan, coeff_index, gauss_jacobi_matrix, gauss_jacobi_rule, gl_nodes,
+                  num_coeffs)
 
-__all__ = ["Plan", "Batch", "Butterfly", "coeff_index", "gl_nodes", "num_coeffs"]
+__all__ = ["Plan", "Batch", "Butterfly", "coeff_index", "gauss_jacobi_matrix", "gauss_jacobi_rule", "gl_nodes",
+           "num_coeffs"]

@@ -132,6 +132,8 @@ SIGNATURES = {
     "sht_bf_block": (_I, [_P, _I, _I, _I, _IP, _IP, ctypes.POINTER(_IP), ctypes.POINTER(_IP),
                           ctypes.POINTER(_DP)]),
     "sht_bf_final": (_I, [_P, _I, _IP, _IP, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_IP)]),
+    "sht_gj_rule": (_I, [_I, _I, _I, _DP, _DP]),
+    "sht_gj_matrix": (_I, [_I, _I, _I, _DP, _I]),
     "sht_profile_enable": (_I, [_P, _I]),
     "sht_profile_reset": (_I, [_P]),
     "sht_profile_count": (_I, [_P]),

@@ -190,9 +190,11 @@ void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pendi
   max_abs_t = std::max(max_abs_t, id_.max_abs_t);
   factor_entries += static_cast<long long>(blk.T.size());
   k_max = std::max(k_max, blk.k);
-  n_ids += 1;
-  sum_k += blk.k;
-  sum_k2 += static_cast<double>(blk.k) * blk.k;
+  if (K > 0) {  // rank statistics over the blocks that exist (a padded tree has empty slots)
+    n_ids += 1;
+    sum_k += blk.k;
+    sum_k2 += static_cast<double>(blk.k) * blk.k;
+  }
   pend.vals.resize(static_cast<size_t>(h) * blk.k);
   pend.gcols.resize(blk.k);
   for (int q = 0; q < blk.k; ++q) {

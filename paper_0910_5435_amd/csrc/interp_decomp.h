@@ -73,7 +73,8 @@ class BfTree {
   const BfBlock& block(int t, int r, int c) const { return blocks_[t][r * ncol(t) + c]; }
   const BfFinal& final_block(int r) const { return finals_[r]; }
 
-  // statistics over every ID (leaves and merges)
+  // rank statistics over every non-empty block (leaves and merges; a padded tree also has
+  // empty slots, which k_max ignores by construction and n_ids / sum_k skip)
   int k_max = 0;
   long long n_ids = 0;
   double sum_k = 0.0, sum_k2 = 0.0;

@@ -1,0 +1,129 @@
+"""The per-order transforms of Section 4 on their own quadratures (host only, no GPU):
+the oracle pinned to closed forms, the library against the oracle, and the butterfly of
+the library's matrices against the rank and accuracy figures printed in Tables 1-6."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gauss_jacobi as gj
+from oracle import gauss_legendre
+from paper_0910_5435_amd import Butterfly, gauss_jacobi_matrix, gauss_jacobi_rule
+from paper_0910_5435_amd import _lib as L
+from tests import bf_reference as bfr
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_tables_ranks.json")
+
+CASES = [(0, 5, 0), (0, 6, 1), (3, 8, 0), (7, 9, 1), (40, 30, 0), (80, 25, 1), (100, 100, 0), (60, 200, 1)]
+
+
+def _moment_errors(x, lam, m, n, parity):
+    # Lemma quadratures: exact for even polynomials of degree <= 4n - 2 (parity 0); the
+    # parity-1 rule also has the node 0, so only monomials vanishing there are checked.
+    ks = range(0, 2 * n) if parity == 0 else range(1, 2 * n + 1)
+    return max(abs(np.sum(lam * x ** (2 * k)) - gj.beta_moment(m, k)) / gj.beta_moment(m, k) for k in ks)
+
+
+# ------------------------------------------------------------------ oracle pins
+@pytest.mark.parametrize("m,n,parity", CASES)
+def test_oracle_rule_is_exact_on_even_polynomials(m, n, parity):
+    x, lam, _ = gj.rule(m, n, parity)
+    assert np.all(np.diff(x) > 0) and x[0] > 0 and x[-1] < 1
+    assert _moment_errors(x, lam, m, n, parity) < 5e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12])
+def test_oracle_order_zero_is_gauss_legendre(n):
+    # m = 0: the zeros of P_{2n} (P_{2n+1}) and the rule over the positive half, each weight
+    # counted for +x and -x, against numpy's Gauss-Legendre rule (textbook routine).
+    for parity in (0, 1):
+        x, lam, _ = gj.rule(0, n, parity)
+        gx, gw = np.polynomial.legendre.leggauss(2 * n + parity)
+        pos = gx > 0
+        assert np.max(np.abs(x - gx[pos])) < 1e-14
+        assert np.max(np.abs(lam - 2.0 * gw[pos]) / lam) < 5e-13  # numpy's edge weights: ~1e-13
+
+
+@pytest.mark.parametrize("m,n,parity", CASES)
+def test_oracle_matrix_is_orthogonal(m, n, parity):
+    A = gj.matrix(m, n, parity)
+    assert np.max(np.abs(A.T @ A - np.eye(n))) < 1e-13
+
+
+def test_oracle_planted_mistake_is_caught():
+    # a dropped factor 2 in the weights, or the wrong degree in the derivative, breaks the
+    # moment identity at once
+    x, lam, _ = gj.rule(5, 10, 0)
+    assert _moment_errors(x, 0.5 * lam, 5, 10, 0) > 0.1
+    xs = x * (1 + 1e-6)
+    assert _moment_errors(xs, lam, 5, 10, 0) > 1e-8
+
+
+# ------------------------------------------------------------------ library vs oracle
+@pytest.mark.parametrize("m,n,parity", CASES)
+def test_library_rule_and_matrix_match_oracle(m, n, parity):
+    x, lam, _ = gj.rule(m, n, parity)
+    xn, ln = gauss_jacobi_rule(m, n, parity)
+    assert np.max(np.abs(xn - x) / x) < 5e-13
+    assert np.max(np.abs(ln - lam) / lam) < 2e-12
+    assert _moment_errors(xn, ln, m, n, parity) < 5e-12
+    assert np.max(np.abs(gauss_jacobi_matrix(m, n, parity) - gj.matrix(m, n, parity))) < 1e-13
+
+
+@pytest.mark.parametrize("parity", [0, 1])
+def test_library_large_order(parity):
+    # m = n = 1250 (the size of the tables' first rows): far beyond the oracle's range, so the
+    # checks are the closed-form low moments, against the Gauss-Legendre nodes of the oracle
+    # for the node count at m = 0, and orthogonality of the whole matrix
+    m = n = 1250
+    x, lam = gauss_jacobi_rule(m, n, parity)
+    assert np.all(np.diff(x) > 0) and 0 < x[0] and x[-1] < 1
+    for k in range(1, 12):
+        ref = gj.beta_moment(m, k)
+        assert abs(np.sum(lam * x ** (2 * k)) - ref) / ref < 1e-11
+    A = gauss_jacobi_matrix(m, n, parity)
+    assert np.max(np.abs(A.T @ A - np.eye(n))) < 1e-12
+    gx, _ = gauss_legendre(2 * 300 + parity)
+    x0, _ = gauss_jacobi_rule(0, 300, parity)
+    assert np.max(np.abs(x0 - gx[gx > 0])) < 1e-14
+
+
+def test_library_argument_validation():
+    lib = L.load()
+    x = np.zeros(4)
+    w = np.zeros(4)
+    P = L._DP
+    assert lib.sht_gj_rule(-1, 4, 0, x.ctypes.data_as(P), w.ctypes.data_as(P)) == L.SHT_EINVAL
+    assert lib.sht_gj_rule(0, 0, 0, x.ctypes.data_as(P), w.ctypes.data_as(P)) == L.SHT_EINVAL
+    assert lib.sht_gj_rule(0, 4, 2, x.ctypes.data_as(P), w.ctypes.data_as(P)) == L.SHT_EINVAL
+    a = np.zeros(16)
+    assert lib.sht_gj_matrix(0, 4, 0, a.ctypes.data_as(P), 3) == L.SHT_EINVAL
+    assert lib.sht_gj_matrix(0, 4, 0, None, 4) == L.SHT_EINVAL
+
+
+# ------------------------------------------------------------------ the paper's tables
+def _rows():
+    return json.load(open(GOLDEN))["rows"]
+
+
+@pytest.mark.parametrize("row", _rows(), ids=lambda r: f"{r['table']}-n{r['n']}-m{r['m']}")
+def test_butterfly_ranks_and_accuracy_match_tables(row):
+    n, m, parity = row["n"], row["m"], row["parity"]
+    A = gauss_jacobi_matrix(m, n, parity)
+    bf = Butterfly(A, json.load(open(GOLDEN))["leaf_width"], 1e-14)
+    rng = np.random.default_rng(0)
+    b = rng.uniform(-1.0, 1.0, n)
+    b /= np.linalg.norm(b)
+    y = bfr.apply(bf, b)[:, 0]
+    e_fwd = np.max(np.abs(y - A @ b))
+    e_inv = np.max(np.abs(bfr.apply_t(bf, y)[:, 0] - b))
+    print(f"n={n} m={m} p={parity}: k_max {bf.k_max} ({row['k_max']}), k_avg {bf.k_avg:.1f} ({row['k_avg']}), "
+          f"k_sigma {bf.k_sd:.1f} ({row['k_sigma']}), eps_fwd {e_fwd:.1e} ({row['eps_fwd']:.1e}), "
+          f"eps_inv {e_inv:.1e} ({row['eps_inv']:.1e})")
+    # the ID details (pivoting, stopping rule) differ from the paper's, so the ranks agree
+    # in their statistics, not block by block
+    assert abs(bf.k_avg - row["k_avg"]) <= 0.1 * row["k_avg"]
+    assert abs(bf.k_sd - row["k_sigma"]) <= 0.15 * row["k_sigma"]
+    assert 0.75 * row["k_max"] <= bf.k_max <= 1.1 * row["k_max"]
+    assert e_fwd <= 10 * row["eps_fwd"] and e_inv <= 10 * row["eps_inv"]
