@@ -404,7 +404,8 @@ def main():
     t_plan = time.perf_counter() - t0
     st = plan.stats()
     print(f"# plan l={l} eps={args.eps} C={args.leaf_width}: {t_plan:.1f} s, k_max={st['k_max']} "
-          f"k_avg={st['k_avg']:.1f} factors={st['factor_entries']:.3e}", file=sys.stderr, flush=True)
+          f"k_avg={st['k_avg']:.1f} factors={st['factor_entries']:.3e} (columns {st['t_columns_s']:.1f} s, "
+          f"IDs {st['t_compress_s']:.1f} s)", file=sys.stderr, flush=True)
 
     beta_np = syn.coefficients(l, F, seed=0, power=args.power)
     beta = torch.from_numpy(beta_np).to("cuda")
@@ -490,7 +491,7 @@ def main():
         "round_trip_rel_err_max": float(np.max(err_rt)),
         "t_plan_s": t_plan,
         "plan": {k: st[k] for k in ("k_max", "k_avg", "k_sd", "factor_entries", "dense_entries",
-                                    "m_max_words", "device_bytes")},
+                                    "m_max_words", "device_bytes", "t_columns_s", "t_compress_s")},
         "wall_s_timed": wall,
         "stages_ms_per_step": stage_totals(prof, args.steps),
         "launches_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},

@@ -21,6 +21,65 @@
 
 namespace sht {
 
+namespace {
+
+// sum_i a[i] b[i] over 16 independent partial sums combined pairwise: a single running
+// sum would be one dependent add chain, which bounds the QR below by add latency.
+double dot(const double* a, const double* b, int n) {
+  double s[16] = {};
+  int i = 0;
+  for (; i + 16 <= n; i += 16)
+    for (int u = 0; u < 16; ++u) s[u] += a[i + u] * b[i + u];
+  for (int u = 0; i < n; ++i, ++u) s[u] += a[i] * b[i];
+  for (int w = 8; w > 0; w /= 2)
+    for (int u = 0; u < w; ++u) s[u] += s[u + w];
+  return s[0];
+}
+
+// b -= c a
+void axpy(double c, const double* a, double* b, int n) {
+  for (int i = 0; i < n; ++i) b[i] -= c * a[i];
+}
+
+// The reflector v applied to four columns at once (v is read once per pass):
+// c_q -= tau (c_q[0] + v . c_q[1:]) [1; v] with v = col[1:].
+typedef double d4 __attribute__((ext_vector_type(4)));
+inline d4 ld4(const double* p) {
+  d4 v;
+  std::memcpy(&v, p, sizeof v);
+  return v;
+}
+inline void st4(double* p, d4 v) { std::memcpy(p, &v, sizeof v); }
+
+void reflect4(double tau, const double* col, double* const c[4], int n) {
+  d4 s0[4] = {}, s1[4] = {};
+  int i = 1;
+  for (; i + 8 <= n; i += 8) {
+    const d4 v0 = ld4(col + i), v1 = ld4(col + i + 4);
+    for (int q = 0; q < 4; ++q) {
+      s0[q] += v0 * ld4(c[q] + i);
+      s1[q] += v1 * ld4(c[q] + i + 4);
+    }
+  }
+  double d[4];
+  for (int q = 0; q < 4; ++q) {
+    const d4 t = s0[q] + s1[q];
+    double r = (t.x + t.z) + (t.y + t.w);
+    for (int e = i; e < n; ++e) r += col[e] * c[q][e];
+    d[q] = tau * (c[q][0] + r);
+    c[q][0] -= d[q];
+  }
+  i = 1;
+  for (; i + 4 <= n; i += 4) {
+    const d4 v = ld4(col + i);
+    for (int q = 0; q < 4; ++q) st4(c[q] + i, ld4(c[q] + i) - d[q] * v);
+  }
+  for (; i < n; ++i)
+    for (int q = 0; q < 4; ++q) c[q][i] -= d[q] * col[i];
+}
+
+}  // namespace
+
 void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult& out,
                    IdWork& w) {
   out.k = 0;
@@ -45,10 +104,7 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
   w.nrm0.assign(n, 0.0);
   for (int j = 0; j < n; ++j) {
     const double* c = a + static_cast<size_t>(j) * m;
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += c[i] * c[i];
-    w.nrm[j] = s;
-    w.nrm0[j] = s;
+    w.nrm[j] = w.nrm0[j] = dot(c, c, m);
   }
   const int kmax = std::min(m, n);
   const double eps2 = eps * eps;
@@ -72,8 +128,7 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
     // Householder reflector H = I - tau v v^T with v = [1; col[s+1:]] zeroing col[s+1:].
     double* col = a + static_cast<size_t>(s) * m;
     const double alpha = col[s];
-    double xn2 = 0.0;
-    for (int i = s + 1; i < m; ++i) xn2 += col[i] * col[i];
+    const double xn2 = dot(col + s + 1, col + s + 1, m - s - 1);
     double tau = 0.0;
     if (xn2 > 0.0) {
       const double beta = -std::copysign(std::sqrt(alpha * alpha + xn2), alpha);
@@ -82,21 +137,25 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
       for (int i = s + 1; i < m; ++i) col[i] *= scale;
       col[s] = beta;
     }
+    int j4 = s + 1;
+    if (tau != 0.0)
+      for (; j4 + 4 <= n; j4 += 4) {
+        double* const c4[4] = {a + static_cast<size_t>(j4) * m + s, a + static_cast<size_t>(j4 + 1) * m + s,
+                               a + static_cast<size_t>(j4 + 2) * m + s, a + static_cast<size_t>(j4 + 3) * m + s};
+        reflect4(tau, col + s, c4, m - s);
+      }
     for (int j = s + 1; j < n; ++j) {
       double* cj = a + static_cast<size_t>(j) * m;
-      if (tau != 0.0) {
-        double dot = cj[s];
-        for (int i = s + 1; i < m; ++i) dot += col[i] * cj[i];
-        dot *= tau;
-        cj[s] -= dot;
-        for (int i = s + 1; i < m; ++i) cj[i] -= dot * col[i];
+      if (tau != 0.0 && j >= j4) {
+        const double d = tau * (cj[s] + dot(col + s + 1, cj + s + 1, m - s - 1));
+        cj[s] -= d;
+        axpy(d, col + s + 1, cj + s + 1, m - s - 1);
       }
       // Downdate the trailing column norm; recompute it exactly once the
       // downdated value has lost too many digits to cancellation.
       double nv = w.nrm[j] - cj[s] * cj[s];
       if (nv < 1e-6 * w.nrm0[j]) {
-        nv = 0.0;
-        for (int i = s + 1; i < m; ++i) nv += cj[i] * cj[i];
+        nv = dot(cj + s + 1, cj + s + 1, m - s - 1);
         w.nrm0[j] = nv;
       }
       w.nrm[j] = nv;
@@ -109,14 +168,15 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
   out.red.assign(w.perm.begin() + k, w.perm.end());
   const int nr = n - k;
   out.T.assign(static_cast<size_t>(k) * nr, 0.0);
-  // T = R11^{-1} R12 by back substitution, one column of R12 at a time.
+  // T = R11^{-1} R12 by back substitution, one column of R12 at a time; once t[i] is known
+  // its multiple of column i of R11 leaves the rows above (contiguous access).
   for (int j = 0; j < nr; ++j) {
-    const double* r12 = a + static_cast<size_t>(k + j) * m;
     double* t = out.T.data() + static_cast<size_t>(j) * k;
+    std::memcpy(t, a + static_cast<size_t>(k + j) * m, sizeof(double) * k);
     for (int i = k - 1; i >= 0; --i) {
-      double v = r12[i];
-      for (int q = i + 1; q < k; ++q) v -= a[static_cast<size_t>(q) * m + i] * t[q];
-      t[i] = v / a[static_cast<size_t>(i) * m + i];
+      const double* ri = a + static_cast<size_t>(i) * m;
+      t[i] /= ri[i];
+      axpy(t[i], ri, t, i);
       out.max_abs_t = std::max(out.max_abs_t, std::fabs(t[i]));
     }
   }
