@@ -29,6 +29,7 @@
 #include <thread>
 #include <vector>
 
+#include "interp_decomp.h"
 #include "sht.h"
 
 namespace {
@@ -115,7 +116,7 @@ std::vector<double> squared_nodes(const Jacobi& J, int n) {
       t[i] = x;
     }
   };
-  const int hw = static_cast<int>(std::max(1u, std::thread::hardware_concurrency()));
+  const int hw = sht::host_thread_count();
   const int nt = std::min(hw, std::max(1, n / 64));
   std::vector<std::thread> th;
   for (int k = 0; k < nt; ++k) th.emplace_back(solve, static_cast<int>(static_cast<long long>(n) * k / nt),
@@ -204,7 +205,7 @@ int sht_gj_matrix(int m, int n, int parity, double* a, int lda) {
       for (int j = 0; j < n; ++j) a[i + static_cast<long long>(j) * lda] = q[j] * inv;
     }
   };
-  const int hw = static_cast<int>(std::max(1u, std::thread::hardware_concurrency()));
+  const int hw = sht::host_thread_count();
   const int nt = std::min(hw, std::max(1, n / 64));
   std::vector<std::thread> th;
   for (int k = 0; k < nt; ++k) th.emplace_back(rows, static_cast<int>(static_cast<long long>(n) * k / nt),

@@ -13,13 +13,28 @@
 // merges, so a column chunk is needed once and then dropped.
 #include "interp_decomp.h"
 
+#include <sched.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 
 namespace sht {
+
+int host_thread_count() {
+  int n = static_cast<int>(std::max(1u, std::thread::hardware_concurrency()));
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof set, &set) == 0) n = std::max(1, CPU_COUNT(&set));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int cap = std::atoi(e);
+    if (cap > 0) n = std::min(n, cap);
+  }
+  return n;
+}
 
 namespace {
 

@@ -20,6 +20,11 @@ struct IdResult {
   double max_abs_t = 0.0;
 };
 
+// Threads for the host precompute when the caller leaves the count to the library: the
+// CPUs this process may run on, capped by OMP_NUM_THREADS when that is set to a positive
+// number (a container's CPU quota does not show in the affinity mask).
+int host_thread_count();
+
 struct IdWork {
   std::vector<double> a;
   std::vector<double> nrm, nrm0;

@@ -101,9 +101,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
     trees[mp].init(l, P->n_cols[mp], C, P->levels[mp], P->eps);
 
   // Device-side column generation, batch by batch.
-  const int nthreads = o.host_threads > 0
-                           ? o.host_threads
-                           : std::max(1u, std::thread::hardware_concurrency());
+  const int nthreads = o.host_threads > 0 ? o.host_threads : host_thread_count();
   const size_t chunk_doubles = static_cast<size_t>(C) * l;
   int batch = static_cast<int>(std::max<size_t>(2, (size_t(64) << 20) / (chunk_doubles * 8)));
   batch = std::min(batch, npairs);
