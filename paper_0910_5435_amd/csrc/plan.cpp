@@ -58,6 +58,78 @@ struct DevBuf {
   }
 };
 
+// The factor pool goes to the device in pack order through two pinned staging buffers
+// (one fills while the other is copied), so the host never holds the whole pool: at
+// l = 1024 that pool is ~7.5 GB, whose first touch alone would cost seconds.  `dev` holds
+// exactly `total` doubles; appending past it is refused rather than written.
+class FactorStream {
+ public:
+  static constexpr size_t kCap = size_t(8) << 20;  // doubles per staging buffer (64 MB)
+  FactorStream(double* dev, size_t total) : dev_(dev), total_(total) {
+    for (int b = 0; b < 2; ++b) {
+      if (err_ == hipSuccess)
+        err_ = hipHostMalloc(reinterpret_cast<void**>(&stage_[b]), kCap * sizeof(double));
+      if (err_ == hipSuccess) err_ = hipEventCreateWithFlags(&ev_[b], hipEventDisableTiming);
+    }
+  }
+  ~FactorStream() {
+    (void)hipStreamSynchronize(nullptr);
+    for (int b = 0; b < 2; ++b) {
+      if (stage_[b]) (void)hipHostFree(stage_[b]);
+      if (ev_[b]) (void)hipEventDestroy(ev_[b]);
+    }
+  }
+  size_t size() const { return off_; }
+  void append(const double* p, size_t n) {
+    if (n == 0) return;
+    if (off_ + n > total_) overrun_ = true;
+    if (overrun_ || err_ != hipSuccess) {
+      off_ += n;
+      return;
+    }
+    while (n > 0 && err_ == hipSuccess) {
+      const size_t take = std::min(n, kCap - fill_);
+      std::memcpy(stage_[cur_] + fill_, p, take * sizeof(double));
+      fill_ += take;
+      p += take;
+      n -= take;
+      off_ += take;
+      if (fill_ == kCap) flush();
+    }
+    off_ += n;  // what a copy error left unsent still counts
+  }
+  // SHT_OK once every appended value is on the device and the count is the one announced.
+  int close() {
+    flush();
+    if (err_ == hipSuccess) err_ = hipStreamSynchronize(nullptr);
+    if (err_ != hipSuccess) return err_ == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
+    return overrun_ || off_ != total_ ? SHT_EINTERNAL : SHT_OK;
+  }
+
+ private:
+  void flush() {
+    if (fill_ == 0) return;
+    if (err_ == hipSuccess)
+      err_ = hipMemcpyAsync(dev_ + sent_, stage_[cur_], fill_ * sizeof(double), hipMemcpyHostToDevice,
+                            nullptr);
+    if (err_ == hipSuccess) err_ = hipEventRecord(ev_[cur_], nullptr);
+    sent_ += fill_;
+    fill_ = 0;
+    cur_ ^= 1;
+    if (err_ == hipSuccess && used_[cur_]) err_ = hipEventSynchronize(ev_[cur_]);  // buffer free again
+    used_[cur_ ^ 1] = true;
+  }
+  double* dev_;
+  size_t total_;
+  double* stage_[2] = {nullptr, nullptr};
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  bool used_[2] = {false, false};
+  size_t off_ = 0, sent_ = 0, fill_ = 0;
+  int cur_ = 0;
+  bool overrun_ = false;
+  hipError_t err_ = hipSuccess;
+};
+
 }  // namespace
 
 // Forward declarations of the pieces of plan construction.
@@ -256,7 +328,16 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   P->rows_v = v_rows;
   P->rows_y = static_cast<long long>(L2) * L2;
 
-  std::vector<double> fac;
+  // Every T and final S of the trees is packed exactly once (empty ones add nothing), so
+  // the pool's size is known before packing starts.
+  size_t n_fac_total = 0;
+  for (const BfTree& T : trees) n_fac_total += static_cast<size_t>(T.factor_entries);
+  {
+    const hipError_t ea = hipMalloc(reinterpret_cast<void**>(&P->d.fac),
+                                    std::max<size_t>(n_fac_total, 2) * sizeof(double));
+    if (ea != hipSuccess) return ea == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
+  }
+  FactorStream fac(P->d.fac, n_fac_total);
   std::vector<uint16_t> idx;
   std::vector<LevelTask> tasks;
   std::vector<FinalTask> finals;
@@ -274,7 +355,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     for (int v : B.skel) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
     for (int v : B.red) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
     fac_off = static_cast<int64_t>(fac.size());
-    fac.insert(fac.end(), B.T.begin(), B.T.end());
+    fac.append(B.T.data(), B.T.size());
     if (!B.T.empty()) fblocks.push_back({fac_off, B.k, B.K - B.k});
   };
   // Tasks of a step are independent; they are grouped into size classes (by input length
@@ -429,7 +510,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     for (int p = 0; p < 2; ++p) {
       const BfFinal& f = *pr.f[p];
       ft.fac[p] = static_cast<int64_t>(fac.size());
-      fac.insert(fac.end(), f.S.begin(), f.S.end());
+      fac.append(f.S.data(), f.S.size());
       if (!f.S.empty()) fblocks.push_back({ft.fac[p], f.h, f.k});
     }
     const int kmx = std::max(ft.k[0], ft.k[1]);
@@ -452,6 +533,10 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   P->n_final = static_cast<long long>(finals.size());
   P->n_fac = static_cast<long long>(fac.size());
   P->n_idx = static_cast<long long>(idx.size());
+  {
+    const int rc = fac.close();
+    if (rc != SHT_OK) return rc;
+  }
   // free host trees early
   std::vector<BfTree>().swap(trees);
 
@@ -483,7 +568,6 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     pd[mp].in_base = P->in_base[mp];
   }
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.fac), fac.data(), fac.size() * sizeof(double));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.idx), idx.data(), idx.size() * sizeof(uint16_t));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.tasks), tasks.data(), tasks.size() * sizeof(LevelTask));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.finals), finals.data(), finals.size() * sizeof(FinalTask));
@@ -492,7 +576,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.D), D.data(), D.size() * sizeof(double));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.twiddle), tw.data(), tw.size() * sizeof(double));
   // transposed copies for the analysis direction, built on the device
-  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.fac_t), nullptr, fac.size() * sizeof(double));
+  if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.fac_t), nullptr, n_fac_total * sizeof(double));
   FactorBlock* dblocks = nullptr;
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&dblocks), fblocks.data(), fblocks.size() * sizeof(FactorBlock));
   if (e == hipSuccess)
@@ -502,7 +586,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   P->n_blocks = static_cast<long long>(fblocks.size());
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   P->stats.device_bytes =
-      static_cast<long long>(2 * fac.size() * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
+      static_cast<long long>(2 * n_fac_total * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
                              finals.size() * sizeof(FinalTask) + pd.size() * sizeof(PairDesc) +
                              (invD.size() + D.size() + tw.size()) * 8);
   return SHT_OK;

@@ -117,6 +117,25 @@ def test_id_blocks_are_interpolative():
             assert len(skel) <= int(np.sum(s > eps * 1e-3)) + 1
 
 
+@pytest.mark.parametrize("rows,cols,C,levels", [(64, 64, 8, -1), (64, 50, 8, -1), (64, 50, 8, 4),
+                                                 (40, 7, 4, -1), (64, 0, 8, 2)])
+def test_factor_entries_count_every_packed_factor(rows, cols, C, levels):
+    # The plan sizes its device factor pool from the trees' factor counts before packing;
+    # that count must be exactly the sum of every interpolation matrix T and every final
+    # skeleton block S, including short last leaves and the empty blocks of a padded tree.
+    rng = np.random.default_rng(3)
+    A = np.linalg.qr(rng.standard_normal((rows, rows)))[0][:, :cols] if cols else np.zeros((rows, 0))
+    bf = Butterfly(A, C, 1e-12, levels=levels)
+    total = 0
+    for t in range(bf.levels + 1):
+        for r in range(2 ** t):
+            for c in range(2 ** (bf.levels - t)):
+                total += bf.block(t, r, c)[2].size
+    for r in range(2 ** bf.levels):
+        total += bf.final(r)[1].size
+    assert bf.factor_entries == total
+
+
 def test_figure_multi_structure_8x8():
     # Figure multi: an 8 x 8 matrix with C = 1 has 4 levels of partitions; every block
     # holds 8 entries: level t (0-based) has 2^t row blocks of 8/2^t rows.
