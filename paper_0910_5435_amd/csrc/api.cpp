@@ -55,6 +55,11 @@ void Profiler::clear() {
   recs.clear();
 }
 
+hipError_t ensure_split_factors(sht_plan_s* P, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(P->split_mu);
+  return split_factors(P, s);
+}
+
 }  // namespace sht
 
 namespace {
@@ -194,7 +199,7 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) return SHT_EHIP;
+  if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const std::string fs = fsuffix(F, precision);
@@ -247,7 +252,7 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) return SHT_EHIP;
+  if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);

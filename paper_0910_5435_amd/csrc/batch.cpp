@@ -414,7 +414,7 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
       g.Rmax = round_up(cw * g.F, 32);
       B->groups.push_back(std::move(g));
     }
-    if (precision != SHT_FP64 && split_factors(P, s) != hipSuccess) rc = SHT_EHIP;
+    if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) rc = SHT_EHIP;
   }
   // launch sets: largest workspaces first, first fit under the limit
   if (rc == SHT_OK) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -206,6 +207,7 @@ struct sht_plan_s {
   long long n_pairs = 0;
   long long n_folded = 0;  // orders whose leaf step is folded into level 1
   sht::DeviceFactors d;
+  std::mutex split_mu;  // serialises the one-time derivation of the split factor copies
   sht_stats stats{};
 };
 
@@ -233,6 +235,8 @@ hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y
                               double* const* fptr = nullptr);
 hipError_t fft_prepare(int l);  // kernel attributes for 4l-point rows (before graph capture)
 hipError_t split_factors(sht_plan_s* P, hipStream_t s);
+// split_factors under the plan's lock: calls from several host threads derive the copies once.
+hipError_t ensure_split_factors(sht_plan_s* P, hipStream_t s);
 bool mfma_ok(int R);
 // coeff (leaf step only, may be null): read the leaf input from (synthesis) or write the
 // leaf output to (transposed) the caller's coefficient array instead of the row buffer.
