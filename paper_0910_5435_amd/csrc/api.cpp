@@ -169,13 +169,18 @@ template <typename Fn>
 int stage(sht_plan_s* P, hipStream_t s, const std::string& name, Work w, Fn&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   int rec = -1;
+  auto fail = [&]() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return SHT_EHIP;
+  };
   if (P->prof.on) {
     rec = P->prof.find_or_add(name, w.flops, w.bytes);
-    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) return SHT_EHIP;
+    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) return fail();
   }
-  if (launch() != hipSuccess) return SHT_EHIP;
+  if (launch() != hipSuccess) return fail();
   if (P->prof.on) {
-    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) return SHT_EHIP;
+    if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) return fail();
     P->prof.pending.push_back({rec, a, b});
   }
   return SHT_OK;
