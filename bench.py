@@ -187,11 +187,44 @@ def time_per_field(plan, beta, steps):
     return e0.elapsed_time(e1)
 
 
+POLAR_TRIM = 1e-15  # |Q| below this on a whole node row: the row is left out of the trimmed GEMM
+
+
+def polar_rows(Q, chunk=256):
+    """Per (m, p): the number of leading nodes (ascending x, equator first) up to the last
+    node whose row of Q^(m,p) (stored transposed, n x l) has an entry above POLAR_TRIM.
+    Towards the pole P^m_k decays like (1 - x^2)^(m/2), so the rows past that node are
+    negligible at high order."""
+    import torch
+
+    npair, _, l = Q.shape
+    idx = torch.arange(1, l + 1, device=Q.device)
+    rows = []
+    for a in range(0, npair, chunk):
+        big = Q[a:a + chunk].abs().amax(dim=1) > POLAR_TRIM  # (pairs, l)
+        rows.append(torch.where(big, idx, torch.zeros_like(idx)).amax(dim=1))
+    return [int(r) for r in torch.cat(rows).tolist()]
+
+
+def gemm_runs(ncols, rows, run=128):
+    """Runs of `run` consecutive pairs, each padded to its largest column count and node
+    count; runs with no work are dropped."""
+    out = []
+    for a in range(0, len(ncols), run):
+        b = min(len(ncols), a + run)
+        n, r = max(ncols[a:b]), max(rows[a:b])
+        if n > 0 and r > 0:
+            out.append((a, b, n, r))
+    return out
+
+
 def gemm_baseline(plan, l, R, steps):
     """Direct FP64 Legendre step on the library DGEMM (torch.bmm): every dense Q^(m,p),
     generated on the device by the plan's column kernel, applied to R columns in synthesis
     (Q X) and in analysis (Q^T Y).  Pairs are taken in runs of 128 consecutive (m, p), each
-    run padded to its largest column count n_p.  Returns times per direction."""
+    run padded to its largest column count n_p.  Timed twice: over all l nodes, and with
+    polar trimming (each run restricted to the nodes where some Q^(m,p) of the run is above
+    POLAR_TRIM).  Returns times per direction."""
     import torch
 
     npair = 4 * l
@@ -202,34 +235,47 @@ def gemm_baseline(plan, l, R, steps):
     g = torch.Generator(device="cuda").manual_seed(0)
     Xt = torch.randn((npair, R, l), dtype=torch.float64, device="cuda", generator=g)
     Y = torch.randn((npair, l, R), dtype=torch.float64, device="cuda", generator=g)
-    runs = [(a, min(npair, a + 128)) for a in range(0, npair, 128)]
-    runs = [(a, b, max(ncols[a:b])) for a, b in runs if max(ncols[a:b]) > 0]
 
-    def synth():
-        for a, b, n in runs:
-            torch.bmm(Xt[a:b, :, :n], Q[a:b, :n, :])
+    def timed(runs):
+        def synth():
+            for a, b, n, r in runs:
+                torch.bmm(Xt[a:b, :, :n], Q[a:b, :n, :r])
 
-    def analysis():
-        for a, b, n in runs:
-            torch.bmm(Q[a:b, :n, :], Y[a:b])
+        def analysis():
+            for a, b, n, r in runs:
+                torch.bmm(Q[a:b, :n, :r], Y[a:b, :r])
 
-    out = {}
-    for name, fn in (("synth", synth), ("analysis", analysis)):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
+        res = {}
+        for name, fn in (("synth", synth), ("analysis", analysis)):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        out[name + "_ms"] = e0.elapsed_time(e1) / steps
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[name + "_ms"] = e0.elapsed_time(e1) / steps
+        return res
+
+    runs = gemm_runs(ncols, [l] * npair)
+    out = timed(runs)
     dense = sum(l * n for n in ncols)
-    padded = sum((b - a) * l * n for a, b, n in runs)
+    padded = sum((b - a) * r * n for a, b, n, r in runs)
     out.update({"dense_entries": dense, "padded_entries": padded,
                 "tflops_synth": 2.0 * padded * R / (out["synth_ms"] / 1e3) / 1e12,
                 "tflops_analysis": 2.0 * padded * R / (out["analysis_ms"] / 1e3) / 1e12})
+    try:
+        rows = polar_rows(Q)
+        truns = gemm_runs(ncols, rows)
+        tr = timed(truns)
+        out["polar_trimmed"] = {
+            "threshold": POLAR_TRIM, "synth_ms": tr["synth_ms"], "analysis_ms": tr["analysis_ms"],
+            "entries": sum(r * n for r, n in zip(rows, ncols)),
+            "padded_entries": sum((b - a) * r * n for a, b, n, r in truns)}
+    except Exception as exc:  # a comparison only: never let it end the run
+        out["polar_trimmed"] = {"error": repr(exc)}
     del Q, Xt, Y
     torch.cuda.empty_cache()
     return out
@@ -450,6 +496,11 @@ def main():
         gemm["pairs_per_s_with_fft"] = F / ((gemm["synth_ms"] + gemm["analysis_ms"] + fft) / 1e3)
         print(f"# dense DGEMM Legendre: synth {gemm['synth_ms']:.1f} ms, analysis {gemm['analysis_ms']:.1f} ms "
               f"(butterfly FP64 {bf['synth']:.1f} / {bf['analysis']:.1f} ms)", file=sys.stderr, flush=True)
+        pt = gemm["polar_trimmed"]
+        if "error" not in pt:
+            print(f"# dense DGEMM Legendre, polar-trimmed ({pt['entries'] / gemm['dense_entries']:.2f} of the "
+                  f"entries): synth {pt['synth_ms']:.1f} ms, analysis {pt['analysis_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
 
     # per-field error of each precision against the FP64 butterfly on the full batch: synthesis
     # of the bench coefficients, and analysis of the FP64 grid
