@@ -6,7 +6,8 @@
 // A P = Q [R11 R12; 0 R22]; the skeleton is the first k pivots and
 // T = R11^{-1} R12 gives A[:, red] ~= A[:, skel] T with error ||R22||.  The rank
 // is the least k with ||R22||_F <= eps (Remark adaptivity; the rank property of
-// Section 2.2 measures blocks in the Frobenius norm).
+// Section 2.2 measures blocks in the Frobenius norm).  Exchanges of skeleton and
+// redundant columns then bring every |T_ij| to at most 2, as the Remark requires.
 //
 // Butterfly (Section 2.2, equations (1)-(6), (top), (bottom)) built depth-first
 // (Section 3): only the skeleton columns of unprocessed blocks are kept between
@@ -93,6 +94,53 @@ void reflect4(double tau, const double* col, double* const c[4], int n) {
     for (int q = 0; q < 4; ++q) c[q][i] -= d[q] * col[i];
 }
 
+// One Householder step on the m x n column-major a at column s: the reflector
+// H = I - tau v v^T with v = [1; a[s+1:, s]] zeroes a[s+1:, s] (v is kept there, the new
+// diagonal entry at a[s, s]) and is applied to columns s+1 .. n-1.
+void householder_step(double* a, int m, int n, int s) {
+  double* col = a + static_cast<size_t>(s) * m;
+  const double alpha = col[s];
+  const double xn2 = dot(col + s + 1, col + s + 1, m - s - 1);
+  if (!(xn2 > 0.0)) return;  // already upper triangular in this column: H = I
+  const double beta = -std::copysign(std::sqrt(alpha * alpha + xn2), alpha);
+  const double tau = (beta - alpha) / beta;
+  const double scale = 1.0 / (alpha - beta);
+  for (int i = s + 1; i < m; ++i) col[i] *= scale;
+  col[s] = beta;
+  int j = s + 1;
+  for (; j + 4 <= n; j += 4) {
+    double* const c4[4] = {a + static_cast<size_t>(j) * m + s, a + static_cast<size_t>(j + 1) * m + s,
+                           a + static_cast<size_t>(j + 2) * m + s, a + static_cast<size_t>(j + 3) * m + s};
+    reflect4(tau, col + s, c4, m - s);
+  }
+  for (; j < n; ++j) {
+    double* cj = a + static_cast<size_t>(j) * m;
+    const double d = tau * (cj[s] + dot(col + s + 1, cj + s + 1, m - s - 1));
+    cj[s] -= d;
+    axpy(d, col + s + 1, cj + s + 1, m - s - 1);
+  }
+}
+
+// T = R11^{-1} R12 (k x (n - k), column-major) from the triangular factor held in the
+// first k rows of a, by back substitution one column at a time; once t[i] is known its
+// multiple of column i of R11 leaves the rows above (contiguous access).  Returns max |T|.
+double solve_t(const double* a, int m, int n, int k, std::vector<double>& T) {
+  const int nr = n - k;
+  T.assign(static_cast<size_t>(k) * nr, 0.0);
+  double mx = 0.0;
+  for (int j = 0; j < nr; ++j) {
+    double* t = T.data() + static_cast<size_t>(j) * k;
+    std::memcpy(t, a + static_cast<size_t>(k + j) * m, sizeof(double) * k);
+    for (int i = k - 1; i >= 0; --i) {
+      const double* ri = a + static_cast<size_t>(i) * m;
+      t[i] /= ri[i];
+      axpy(t[i], ri, t, i);
+      mx = std::max(mx, std::fabs(t[i]));
+    }
+  }
+  return mx;
+}
+
 }  // namespace
 
 void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult& out,
@@ -140,32 +188,9 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
       std::swap(w.nrm[s], w.nrm[p]);
       std::swap(w.nrm0[s], w.nrm0[p]);
     }
-    // Householder reflector H = I - tau v v^T with v = [1; col[s+1:]] zeroing col[s+1:].
-    double* col = a + static_cast<size_t>(s) * m;
-    const double alpha = col[s];
-    const double xn2 = dot(col + s + 1, col + s + 1, m - s - 1);
-    double tau = 0.0;
-    if (xn2 > 0.0) {
-      const double beta = -std::copysign(std::sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      const double scale = 1.0 / (alpha - beta);
-      for (int i = s + 1; i < m; ++i) col[i] *= scale;
-      col[s] = beta;
-    }
-    int j4 = s + 1;
-    if (tau != 0.0)
-      for (; j4 + 4 <= n; j4 += 4) {
-        double* const c4[4] = {a + static_cast<size_t>(j4) * m + s, a + static_cast<size_t>(j4 + 1) * m + s,
-                               a + static_cast<size_t>(j4 + 2) * m + s, a + static_cast<size_t>(j4 + 3) * m + s};
-        reflect4(tau, col + s, c4, m - s);
-      }
+    householder_step(a, m, n, s);
     for (int j = s + 1; j < n; ++j) {
-      double* cj = a + static_cast<size_t>(j) * m;
-      if (tau != 0.0 && j >= j4) {
-        const double d = tau * (cj[s] + dot(col + s + 1, cj + s + 1, m - s - 1));
-        cj[s] -= d;
-        axpy(d, col + s + 1, cj + s + 1, m - s - 1);
-      }
+      const double* cj = a + static_cast<size_t>(j) * m;
       // Downdate the trailing column norm; recompute it exactly once the
       // downdated value has lost too many digits to cancellation.
       double nv = w.nrm[j] - cj[s] * cj[s];
@@ -179,22 +204,38 @@ void interp_decomp(const double* A, int m, int n, int lda, double eps, IdResult&
   }
   const int k = s;
   out.k = k;
+  out.max_abs_t = solve_t(a, m, n, k, out.T);
+  // Remark QR_algorithm asks for interpolation coefficients of magnitude at most 2, which
+  // column pivoting nearly always gives.  Where it does not, the skeleton column i and the
+  // redundant column j of the largest |T_ij| > 2 are exchanged (the Gu-Eisenstat step:
+  // |det R11| grows by |T_ij| each time, so no exchange repeats), and the block is factored
+  // again without pivoting in the new order.  An exchange whose residual ||R22||_F would
+  // exceed eps is not taken.
+  for (int it = 0; it < 64 && k > 0 && k < n && out.max_abs_t > 2.0; ++it) {
+    size_t arg = 0;
+    for (size_t q = 1; q < out.T.size(); ++q)
+      if (std::fabs(out.T[q]) > std::fabs(out.T[arg])) arg = q;
+    const int i = static_cast<int>(arg % k), j = static_cast<int>(arg / k);
+    w.trial = w.perm;
+    std::swap(w.trial[i], w.trial[k + j]);
+    w.b.resize(static_cast<size_t>(m) * n);
+    for (int c = 0; c < n; ++c)
+      std::memcpy(&w.b[static_cast<size_t>(c) * m], A + static_cast<size_t>(w.trial[c]) * lda,
+                  sizeof(double) * m);
+    for (int q = 0; q < k; ++q) householder_step(w.b.data(), m, n, q);
+    double resid = 0.0;
+    for (int c = k; c < n; ++c) {
+      const double* col = w.b.data() + static_cast<size_t>(c) * m;
+      resid += dot(col + k, col + k, m - k);
+    }
+    if (resid > eps2) break;
+    w.perm.swap(w.trial);
+    w.a.swap(w.b);
+    a = w.a.data();
+    out.max_abs_t = solve_t(a, m, n, k, out.T);
+  }
   out.skel.assign(w.perm.begin(), w.perm.begin() + k);
   out.red.assign(w.perm.begin() + k, w.perm.end());
-  const int nr = n - k;
-  out.T.assign(static_cast<size_t>(k) * nr, 0.0);
-  // T = R11^{-1} R12 by back substitution, one column of R12 at a time; once t[i] is known
-  // its multiple of column i of R11 leaves the rows above (contiguous access).
-  for (int j = 0; j < nr; ++j) {
-    double* t = out.T.data() + static_cast<size_t>(j) * k;
-    std::memcpy(t, a + static_cast<size_t>(k + j) * m, sizeof(double) * k);
-    for (int i = k - 1; i >= 0; --i) {
-      const double* ri = a + static_cast<size_t>(i) * m;
-      t[i] /= ri[i];
-      axpy(t[i], ri, t, i);
-      out.max_abs_t = std::max(out.max_abs_t, std::fabs(t[i]));
-    }
-  }
 }
 
 int butterfly_depth(int cols, int C) {

@@ -26,14 +26,15 @@ struct IdResult {
 int host_thread_count();
 
 struct IdWork {
-  std::vector<double> a;
+  std::vector<double> a, b;  // the block being factored; b: a refactoring after an exchange
   std::vector<double> nrm, nrm0;
-  std::vector<int> perm;
+  std::vector<int> perm, trial;
 };
 
 // Rank chosen adaptively (Remark adaptivity): the least k whose residual block
-// R22 of the pivoted QR has Frobenius norm <= eps.  a is rows x cols,
-// column-major with leading dimension lda.
+// R22 of the pivoted QR has Frobenius norm <= eps; skeleton exchanges then bound
+// |T| by 2 (Remark QR_algorithm) without giving up that residual bound.  a is
+// rows x cols, column-major with leading dimension lda.
 void interp_decomp(const double* a, int rows, int cols, int lda, double eps, IdResult& out,
                    IdWork& work);
 

@@ -66,3 +66,33 @@ def apply_t(bf, y):
         seg[red] = T.T @ v
         x[c * C : c * C + seg.shape[0]] = seg
     return x
+
+
+def blocks_with_inputs(bf, A):
+    """Every ID of the butterfly with the matrix it was computed from: yields
+    (t, r, c, M, skel, red, T), where M holds the rows of row node r at level t and the
+    columns that entered block (t, r, c) (a leaf's own columns, or the skeleton columns of
+    its two children at level t - 1, left then right), taken from the dense A."""
+    L, C = bf.levels, bf.C
+    rows = {(0, 0): (0, bf.rows)}
+    for t in range(1, L + 1):
+        for q in range(2 ** (t - 1)):
+            lo, h = rows[(t - 1, q)]
+            top = (h + 1) // 2
+            rows[(t, 2 * q)] = (lo, top)
+            rows[(t, 2 * q + 1)] = (lo + top, h - top)
+    gcols = {}
+    for c in range(2 ** L):
+        skel, red, T = bf.block(0, 0, c)
+        inp = np.arange(c * C, c * C + len(skel) + len(red))
+        gcols[(0, 0, c)] = inp[skel]
+        yield 0, 0, c, A[:, inp], skel, red, T
+    for t in range(1, L + 1):
+        for q in range(2 ** (t - 1)):
+            for cc in range(2 ** (L - t)):
+                inp = np.concatenate([gcols[(t - 1, q, 2 * cc)], gcols[(t - 1, q, 2 * cc + 1)]])
+                for r in (2 * q, 2 * q + 1):
+                    skel, red, T = bf.block(t, r, cc)
+                    lo, h = rows[(t, r)]
+                    gcols[(t, r, cc)] = inp[skel]
+                    yield t, r, cc, A[lo:lo + h][:, inp], skel, red, T
