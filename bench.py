@@ -542,7 +542,8 @@ def main():
         "round_trip_rel_err_max": float(np.max(err_rt)),
         "t_plan_s": t_plan,
         "plan": {k: st[k] for k in ("k_max", "k_avg", "k_sd", "factor_entries", "dense_entries",
-                                    "m_max_words", "device_bytes", "t_columns_s", "t_compress_s")},
+                                    "m_max_words", "device_bytes", "t_columns_s", "t_compress_s",
+                                    "max_abs_t")},
         "wall_s_timed": wall,
         "stages_ms_per_step": stage_totals(prof, args.steps),
         "launches_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},

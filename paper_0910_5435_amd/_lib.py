@@ -51,6 +51,7 @@ class Stats(ctypes.Structure):
         ("t_total_s", ctypes.c_double),
         ("eps", ctypes.c_double),
         ("device_bytes", ctypes.c_longlong),
+        ("max_abs_t", ctypes.c_double),
     ]
 
 

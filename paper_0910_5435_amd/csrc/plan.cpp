@@ -265,7 +265,9 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   double sk = 0, sk2 = 0;
   int kmax = 0;
   long long fe = 0, mmax = 0, dense = 0;
+  double tmax = 0.0;
   for (auto& t : trees) {
+    tmax = std::max(tmax, t.max_abs_t);
     nid += t.n_ids;
     sk += t.sum_k;
     sk2 += t.sum_k2;
@@ -281,6 +283,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   st.factor_entries = fe;
   st.dense_entries = dense;
   st.m_max_words = mmax;
+  st.max_abs_t = tmax;
   st.t_columns_s = t_cols;
   st.t_compress_s = t_comp;
   int rc = pack_plan(P, trees);
