@@ -15,7 +15,8 @@ from tests import bf_reference as bfr
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_tables_ranks.json")
 
-CASES = [(0, 5, 0), (0, 6, 1), (3, 8, 0), (7, 9, 1), (40, 30, 0), (80, 25, 1), (100, 100, 0), (60, 200, 1)]
+CASES = [(0, 1, 0), (0, 1, 1), (500, 1, 0), (500, 2, 1), (0, 5, 0), (0, 6, 1), (3, 8, 0), (7, 9, 1), (40, 30, 0),
+         (80, 25, 1), (100, 100, 0), (60, 200, 1)]
 
 
 def _moment_errors(x, lam, m, n, parity):
