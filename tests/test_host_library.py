@@ -4,6 +4,7 @@ import ctypes
 import math
 import os
 import re
+import shutil
 import subprocess
 
 import numpy as np
@@ -35,6 +36,47 @@ def test_library_exports_every_declared_function():
         assert n in exported, n
         assert hasattr(lib, n)
         assert n in L.SIGNATURES, f"binding lacks {n}"
+
+
+C_PROGRAM = r"""
+#include <math.h>
+#include <stdio.h>
+#include "sht.h"
+int main(void) {
+  sht_plan_opts o;
+  sht_plan_t p = 0;
+  double x[8], w[8], s = 0.0;
+  int i;
+  sht_default_opts(&o);
+  if (o.leaf_width != 64 || o.precision != SHT_FP64) return 1;
+  if (sht_num_coeffs(4, SHT_COMPLEX) != 64 || sht_coeff_index(4, 7, -7, SHT_COMPLEX) != 63) return 2;
+  if (sht_gl_nodes(8, x, w) != SHT_OK) return 3;
+  for (i = 0; i < 8; ++i) s += w[i];
+  if (fabs(s - 2.0) > 1e-14) return 4;
+  if (sht_gj_rule(3, 4, 1, x, w) != SHT_OK || !(x[0] > 0.0 && x[3] < 1.0)) return 5;
+  if (sht_plan(0, 1e-12, &p) != SHT_EINVAL || p != 0) return 6;  /* rejected before any GPU call */
+  if (!sht_strerror(SHT_EINVAL)) return 7;
+  printf("ok\n");
+  return 0;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    # The boundary is a C ABI: the header must compile as strict C99 and a C program must link
+    # against the library and call its host-side entry points (no GPU needed for these).
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    lib_dir = os.path.dirname(L.load()._name)
+    exe = tmp_path / "abi"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", lib_dir, "-lsht", f"-Wl,-rpath,{lib_dir}", "-lm", "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.returncode, r.stdout, r.stderr)
+
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 64, 513, 2048])
