@@ -90,6 +90,18 @@ def test_library_large_order(parity):
     assert np.max(np.abs(x0 - gx[gx > 0])) < 1e-14
 
 
+def test_library_matrix_leading_dimension():
+    # column-major with lda > n: the first n rows of every column are the matrix, the padding
+    # rows are left as they were
+    lib = L.load()
+    m, n, parity, lda = 9, 7, 1, 10
+    a = np.full(lda * n, 7.5)
+    assert lib.sht_gj_matrix(m, n, parity, a.ctypes.data_as(L._DP), lda) == L.SHT_OK
+    a = a.reshape(n, lda).T  # (lda, n)
+    assert np.all(a[n:] == 7.5)
+    assert np.max(np.abs(a[:n] - gj.matrix(m, n, parity))) < 1e-13
+
+
 def test_library_argument_validation():
     lib = L.load()
     x = np.zeros(4)
