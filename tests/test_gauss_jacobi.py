@@ -2,6 +2,7 @@
 the oracle pinned to closed forms, the library against the oracle, and the butterfly of
 the library's matrices against the rank and accuracy figures printed in Tables 1-6."""
 import json
+import math
 import os
 
 import numpy as np
@@ -52,6 +53,18 @@ def test_oracle_matrix_is_orthogonal(m, n, parity):
     assert np.max(np.abs(A.T @ A - np.eye(n))) < 1e-13
 
 
+def test_oracle_beta_moment():
+    # closed values (m = 0: 2 / (2k + 1); m = 1, k = 0: 4/3) and mpmath's Beta function
+    mpmath = pytest.importorskip("mpmath")
+    for k in range(6):
+        assert abs(gj.beta_moment(0, k) - 2.0 / (2 * k + 1)) <= 1e-16
+    assert abs(gj.beta_moment(1, 0) - 4.0 / 3.0) <= 1e-16
+    mpmath.mp.dps = 30
+    for m, k in [(3, 2), (1250, 7), (10000, 11), (40000, 5)]:
+        ref = mpmath.beta(k + mpmath.mpf(1) / 2, m + 1)
+        assert abs(gj.beta_moment(m, k) - ref) / ref < 1e-14
+
+
 def test_oracle_planted_mistake_is_caught():
     # a dropped factor 2 in the weights, or the wrong degree in the derivative, breaks the
     # moment identity at once
@@ -66,10 +79,10 @@ def test_oracle_planted_mistake_is_caught():
 def test_library_rule_and_matrix_match_oracle(m, n, parity):
     x, lam, _ = gj.rule(m, n, parity)
     xn, ln = gauss_jacobi_rule(m, n, parity)
-    assert np.max(np.abs(xn - x) / x) < 5e-13
-    assert np.max(np.abs(ln - lam) / lam) < 2e-12
+    assert np.max(np.abs(xn - x) / x) < 5e-15
+    assert np.max(np.abs(ln - lam) / lam) < 1e-12  # the oracle's weights carry (1 - x^2)^{+-m}
     assert _moment_errors(xn, ln, m, n, parity) < 5e-12
-    assert np.max(np.abs(gauss_jacobi_matrix(m, n, parity) - gj.matrix(m, n, parity))) < 1e-13
+    assert np.max(np.abs(gauss_jacobi_matrix(m, n, parity) - gj.matrix(m, n, parity))) < 5e-14
 
 
 @pytest.mark.parametrize("parity", [0, 1])
@@ -80,14 +93,32 @@ def test_library_large_order(parity):
     m = n = 1250
     x, lam = gauss_jacobi_rule(m, n, parity)
     assert np.all(np.diff(x) > 0) and 0 < x[0] and x[-1] < 1
-    for k in range(1, 12):
+    for k in range(0 if parity == 0 else 1, 12):  # the parity-1 rule leaves out the node 0
         ref = gj.beta_moment(m, k)
-        assert abs(np.sum(lam * x ** (2 * k)) - ref) / ref < 1e-11
+        assert abs(math.fsum(lam * x ** (2 * k)) - ref) / ref < 1e-13
     A = gauss_jacobi_matrix(m, n, parity)
     assert np.max(np.abs(A.T @ A - np.eye(n))) < 1e-12
     gx, _ = gauss_legendre(2 * 300 + parity)
     x0, _ = gauss_jacobi_rule(0, 300, parity)
     assert np.max(np.abs(x0 - gx[gx > 0])) < 1e-14
+
+
+@pytest.mark.parametrize("parity", [0, 1])
+def test_library_nodes_near_the_equator(parity):
+    # m = 0, n = 1500: the rule is the positive half of the 3000- (3001-) point Gauss-Legendre
+    # rule, here from the oracle's Newton iteration on the textbook recurrence.  The smallest
+    # nodes (t = x^2 ~ 3e-7) are where an iteration in t alone loses digits (t - d_l keeps
+    # only the leading bits of t).  Towards the pole the weight of a node moves with the
+    # node's own last bit by ~u / (1 - x) relative, in either rule, hence the tolerance; both
+    # sides' weights are within ~2e-13 of high-precision values elsewhere (checked with mpmath).
+    n = 1500
+    x, lam = gauss_jacobi_rule(0, n, parity)
+    gx, gw = gauss_legendre(2 * n + parity)
+    pos = gx > 0
+    assert np.max(np.abs(x - gx[pos]) / gx[pos]) < 2e-14
+    assert np.all(np.abs(lam - 2.0 * gw[pos]) / lam <= 3e-13 + 4e-16 / (1.0 - x))
+    total = math.fsum(lam) + (math.fsum(gw[gx == 0]) if parity else 0.0)  # add the node 0 back
+    assert abs(total - gj.beta_moment(0, 0)) < 1e-13
 
 
 def test_library_matrix_leading_dimension():
