@@ -62,6 +62,36 @@ int main(void) {
 """
 
 
+STRUCTS = {"sht_plan_opts": "PlanOpts", "sht_stats": "Stats", "sht_request": "Request",
+           "sht_batch_config": "BatchConfig", "sht_batch_info": "BatchInfo"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # The ctypes mirrors of the header's structs must have the C sizes and field offsets:
+    # a C program compiled against the header prints them.
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sht.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(L, pyname)._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(L, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
 def test_header_is_plain_c_and_links(tmp_path):
     # The boundary is a C ABI: the header must compile as strict C99 and a C program must link
     # against the library and call its host-side entry points (no GPU needed for these).
