@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-12)
     ap.add_argument("--power", type=float, default=1.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-orders", type=int, default=24)
+    ap.add_argument("--cpu-orders", type=int, default=48)
     ap.add_argument("--cpu-fields", type=int, default=4,
                     help="fields in the oracle sample (a multiple of 4 for the matrix-core variants)")
     ap.add_argument("--workload", default="metric", choices=["metric", "mixed", "single"],
