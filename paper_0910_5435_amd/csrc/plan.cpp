@@ -8,7 +8,8 @@
 //     a time, and each chunk is consumed at once by the depth-first butterfly
 //     construction (Section 3), so no (m, p) ever holds its full matrix.
 //  3. The resulting IDs are packed step by step (leaves, then each merge level,
-//     then the final skeletons) so the apply kernels stream them in order.
+//     then the final skeletons) so the apply kernels stream them in order; the
+//     factor values go to the device as they are packed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
