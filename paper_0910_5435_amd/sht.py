@@ -44,6 +44,14 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _used_on(stream, *tensors):
+    """Tell torch's caching allocator that tensors it allocated on the current stream are
+    used on another stream, so their memory is not handed out again before that work ends."""
+    if stream is not None:
+        for t in tensors:
+            t.record_stream(stream)
+
+
 class Plan:
     """Butterfly SHT plan for bandlimit l (degrees 0..2l-1) on one GPU."""
 
@@ -187,7 +195,11 @@ class Plan:
         return self.kind == "complex"
 
     def synth(self, coeff, out=None, precision=None, stream=None):
-        """coeff: complex128 (F, n_coeffs) on the device -> grid (F, 2l, 4l)."""
+        """coeff: complex128 (F, n_coeffs) on the device -> grid (F, 2l, 4l).
+
+        stream (a torch stream; default the current one) is where the kernels run.  Calls on
+        one plan share its cached workspace, so calls on different streams must be ordered
+        by the caller."""
         torch = _torch()
         if coeff.dim() == 1:
             coeff = coeff.unsqueeze(0)
@@ -199,6 +211,7 @@ class Plan:
         self._check_tensor(out, self.grid_shape, self._grid_complex(), "grid")
         prec = PRECISIONS[precision or self.precision]
         ws = self.workspace(F, precision, coeff.device)
+        _used_on(stream, ws, out)
         L.check(L.load().sht_synth_ex(self._h, prec, ctypes.c_void_p(coeff.data_ptr()),
                                       ctypes.c_void_p(out.data_ptr()), F,
                                       ctypes.c_void_p(_align(ws.data_ptr())), ws.numel() - 256,
@@ -216,6 +229,7 @@ class Plan:
         self._check_tensor(out, (self.n_coeffs,), True, "coeff")
         prec = PRECISIONS[precision or self.precision]
         ws = self.workspace(F, precision, grid.device)
+        _used_on(stream, ws, out)
         L.check(fn(self._h, prec, ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                    F, ctypes.c_void_p(_align(ws.data_ptr())), ws.numel() - 256,
                    _stream_handle(stream)), what)
