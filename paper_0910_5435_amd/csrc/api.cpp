@@ -595,7 +595,7 @@ int sht_bf_build(const double* a, int rows, int cols, int lda, int leaf_width, i
   if (rows < 1 || cols < 0 || lda < rows || leaf_width < 1 || !(eps > 0.0) || (!a && cols > 0))
     return SHT_EINVAL;
   int L = levels < 0 ? butterfly_depth(cols, leaf_width) : levels;
-  if ((1LL << L) * leaf_width < cols || (1 << L) > rows) return SHT_EINVAL;
+  if (L > 24 || (1LL << L) * leaf_width < cols || (1LL << L) > rows) return SHT_EINVAL;
   sht_bf_s* bf = new (std::nothrow) sht_bf_s();
   if (!bf) return SHT_ENOMEM;
   try {

@@ -318,5 +318,7 @@ def test_argument_validation_without_gpu():
     bfh = ctypes.c_void_p()
     assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 2, 1, -1, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
     assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 4, 1, 5, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
+    for levels in (25, 40, 100):  # depths beyond the tree's limit, whatever the row count
+        assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 4, 1, levels, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
     assert lib.sht_strerror(L.SHT_EHIP) == b"HIP runtime error"
     assert lib.sht_version()
