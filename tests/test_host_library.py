@@ -62,6 +62,24 @@ int main(void) {
 """
 
 
+def test_host_code_under_sanitizers(tmp_path):
+    # The host C++ (IDs, butterflies, per-order rules, Gauss-Legendre) built with address and
+    # undefined-behaviour sanitizers and driven over many shapes; any report fails the run.
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("no clang++ with sanitizer runtimes")
+    csrc = os.path.join(ROOT, "paper_0910_5435_amd", "csrc")
+    exe = tmp_path / "drv"
+    # host-only sources; -Xarch_host keeps the sanitizer flags on the host side of the driver
+    subprocess.run([clang, "-std=c++17", "-O1", "-g", "-march=x86-64-v3", "-Xarch_host", "-fsanitize=address,undefined",
+                    "-Xarch_host", "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+                    os.path.join(ROOT, "tests", "host_sanitize_driver.cpp"),
+                    os.path.join(csrc, "interp_decomp.cpp"), os.path.join(csrc, "gauss_jacobi.cpp"),
+                    os.path.join(csrc, "gl_nodes.cpp"), "-lpthread", "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and r.stdout.strip() == "drv ok", (r.returncode, r.stdout, r.stderr[-2000:])
+
+
 STRUCTS = {"sht_plan_opts": "PlanOpts", "sht_stats": "Stats", "sht_request": "Request",
            "sht_batch_config": "BatchConfig", "sht_batch_info": "BatchInfo"}
 
