@@ -1,5 +1,5 @@
 """CPU tests of the benchmark's pure helpers: the row ranges of the polar-trimmed dense GEMM
-comparison.  No GPU."""
+comparison, the roofline object of the JSON line and the per-step stage totals.  No GPU."""
 import numpy as np
 import torch
 
@@ -45,3 +45,29 @@ def test_gemm_runs_pad_to_the_run_maximum():
     rows = [8, 6, 0, 0, 2, 7, 0]
     assert bench.gemm_runs(ncols, rows, run=2) == [(0, 2, 5, 8), (4, 6, 3, 7)]
     assert bench.gemm_runs(ncols, [0] * 7, run=3) == []
+
+
+def test_roofline_picks_the_largest_launch_and_its_bound():
+    prof = {
+        "synth.fft/F64/split32": {"ms": 40.0, "launches": 20, "flops": 1e9, "bytes": 8e9},
+        "analysis.final/F64/split32": {"ms": 250.0, "launches": 20, "flops": 1.2e11, "bytes": 1.5e10},
+        "synth.level2.c0/F64/split32": {"ms": 100.0, "launches": 20, "flops": 4e11, "bytes": 1e10},
+    }
+    r = bench.roofline(prof, ms_total=500.0, precision="split32")
+    mean_s = 250.0 / 20 / 1e3
+    # 8 flop/byte is below the FP32 ridge (157.3 / 8 = 19.7): bandwidth-bound
+    assert r["kernel"] == "analysis.final/F64/split32" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 1.5e10 / mean_s / 1e9) < 1e-9 and r["peak"] == 8000.0
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    assert abs(r["share_of_step"] - 0.5) < 1e-12 and r["mean_launch_ms"] == 12.5
+    # the same launch with 40 flop/byte in FP64 is above the FP64 ridge (9.8): matrix-core bound
+    prof["analysis.final/F64/split32"]["flops"] = 6e11
+    r = bench.roofline(prof, ms_total=500.0, precision="fp64")
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert abs(r["achieved"] - 6e11 / mean_s / 1e12) < 1e-9
+
+
+def test_stage_totals_merge_size_classes():
+    prof = {"synth.level2.c0/F64/fp64": {"ms": 30.0}, "synth.level2.c1/F64/fp64": {"ms": 10.0},
+            "synth.fft/F64/fp64": {"ms": 20.0}}
+    assert bench.stage_totals(prof, steps=10) == {"synth.fft/F64/fp64": 2.0, "synth.level2/F64/fp64": 4.0}
