@@ -27,8 +27,8 @@ def test_gl_small_closed_forms():
     np.testing.assert_allclose(x, [-1 / math.sqrt(3), 1 / math.sqrt(3)], rtol=0, atol=3e-16)
     np.testing.assert_allclose(w, [1.0, 1.0], rtol=0, atol=1e-15)
     x, w = oracle.gauss_legendre(3)
-    np.testing.assert_allclose(x, [-math.sqrt(0.6), 0.0, math.sqrt(0.6)], atol=3e-16)
-    np.testing.assert_allclose(w, [5 / 9, 8 / 9, 5 / 9], atol=1e-15)
+    np.testing.assert_allclose(x, [-math.sqrt(0.6), 0.0, math.sqrt(0.6)], rtol=0, atol=3e-16)
+    np.testing.assert_allclose(w, [5 / 9, 8 / 9, 5 / 9], rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 10, 64, 128, 256])
@@ -199,14 +199,14 @@ def test_orthonormal_columns_all_orders(l):
             n = Q.shape[1]
             assert n == oracle.folded_sizes(l, m)[p]
             if n:
-                np.testing.assert_allclose(Q.T @ Q, np.eye(n), atol=2e-14)
+                np.testing.assert_allclose(Q.T @ Q, np.eye(n), rtol=0, atol=2e-14)
 
 
 @pytest.mark.parametrize("m", [0, 333, 700, 1023])
 def test_orthonormal_columns_l512(m):
     for p in (0, 1):
         Q = oracle.dense_q(512, m, p)
-        np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=5e-13)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), rtol=0, atol=5e-13)
 
 
 # ---------------------------------------------------------------- layout
@@ -233,17 +233,17 @@ def test_worked_example_l1():
     g = json.load(open(os.path.join(HERE, "golden", "l1_worked_example.json")))
     l = g["l"]
     x, w = oracle.gauss_legendre(2 * l)
-    np.testing.assert_allclose(x, g["nodes"], atol=3e-16)
-    np.testing.assert_allclose(w, g["weights"], atol=1e-15)
+    np.testing.assert_allclose(x, g["nodes"], rtol=0, atol=3e-16)
+    np.testing.assert_allclose(w, g["weights"], rtol=0, atol=1e-15)
     for case in g["cases"]:
         beta = np.zeros((1, oracle.n_coeffs(l)), dtype=complex)
         beta[0, oracle.coeff_index(l, case["k"], case["m"])] = 1.0
         ref = np.array(case["grid_re"]) + 1j * np.array(case["grid_im"])
         for direct in (False, True):
             f = oracle.synth(beta, l, direct=direct)[0]
-            np.testing.assert_allclose(f, ref, atol=1e-15)
+            np.testing.assert_allclose(f, ref, rtol=0, atol=1e-15)
         back = oracle.analyze(ref[None], l)
-        np.testing.assert_allclose(back, beta, atol=1e-15)
+        np.testing.assert_allclose(back, beta, rtol=0, atol=1e-15)
 
 
 def test_against_scipy_spherical_harmonics():
@@ -263,7 +263,7 @@ def test_against_scipy_spherical_harmonics():
         Y = sps.sph_harm_y(int(k), am, T, PH)
         basis = math.sqrt(2 * math.pi) * (-1) ** am * (Y if m >= 0 else np.conj(Y))
         ref += beta[:, pos][:, None, None] * basis[None]
-    np.testing.assert_allclose(f, ref, atol=1e-13)
+    np.testing.assert_allclose(f, ref, rtol=0, atol=1e-13)
 
 
 @pytest.mark.parametrize("l", [1, 2, 3, 5, 8, 16])
@@ -275,7 +275,7 @@ def test_round_trip_exact(l, kind, grid):
     if kind == "real":
         assert np.isrealobj(f)
     back = oracle.analyze(f, l, kind=kind, grid=grid)
-    np.testing.assert_allclose(back, beta, atol=1e-13 * np.max(np.abs(beta)))
+    np.testing.assert_allclose(back, beta, rtol=0, atol=1e-13 * np.max(np.abs(beta)))
 
 
 @pytest.mark.parametrize("l", [2, 8, 32])
@@ -283,8 +283,8 @@ def test_fft_equals_direct_sum(l):
     beta = syn.coefficients(l, 2, seed=11)
     f1 = oracle.synth(beta, l, direct=False)
     f2 = oracle.synth(beta, l, direct=True)
-    np.testing.assert_allclose(f1, f2, atol=1e-12)
-    np.testing.assert_allclose(oracle.analyze(f1, l, direct=True), oracle.analyze(f1, l), atol=1e-13)
+    np.testing.assert_allclose(f1, f2, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.analyze(f1, l, direct=True), oracle.analyze(f1, l), rtol=0, atol=1e-13)
 
 
 @pytest.mark.parametrize("kind", ["complex", "real"])
@@ -303,12 +303,12 @@ def test_subset_routines_agree_with_full():
     beta = syn.coefficients(l, 2, seed=9)
     f = oracle.synth(beta, l)
     rings = [0, 5, 2 * l - 1]
-    np.testing.assert_allclose(oracle.ring_values(beta, l, rings), f[:, rings], atol=1e-14)
+    np.testing.assert_allclose(oracle.ring_values(beta, l, rings), f[:, rings], rtol=0, atol=1e-14)
     keep = [0, 2, 5]
     masked = beta.copy()
     ms = syn.orders_canonical(l)
     masked[:, ~np.isin(np.abs(ms), keep)] = 0.0
-    np.testing.assert_allclose(oracle.synth(beta, l, orders=keep), oracle.synth(masked, l), atol=1e-14)
+    np.testing.assert_allclose(oracle.synth(beta, l, orders=keep), oracle.synth(masked, l), rtol=0, atol=1e-14)
     full = oracle.analyze(f, l)
     part = oracle.analyze_orders(f, l, [0, 3, -7])
     for m in [0, 3, -3, 7, -7]:
@@ -318,7 +318,7 @@ def test_subset_routines_agree_with_full():
     adj_full = oracle.synth_adjoint(f, l)
     adj_part = oracle.synth_adjoint(f, l, orders=[0, 3])
     sel = np.isin(np.abs(ms), [0, 3])
-    np.testing.assert_allclose(adj_part[:, sel], adj_full[:, sel], atol=1e-13)
+    np.testing.assert_allclose(adj_part[:, sel], adj_full[:, sel], rtol=0, atol=1e-13)
     assert np.all(adj_part[:, ~sel] == 0)
 
 
