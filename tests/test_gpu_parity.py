@@ -123,7 +123,7 @@ def test_worked_example_l1_on_gpu():
         beta[0, oracle.coeff_index(1, case["k"], case["m"])] = 1.0
         ref = np.array(case["grid_re"]) + 1j * np.array(case["grid_im"])
         got = P.synth(_dev(beta)).cpu().numpy()[0]
-        np.testing.assert_allclose(got, ref, atol=1e-15)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
 
 
 @pytest.mark.parametrize("l,C,F", [(32, 8, 2), (128, 64, 1), (64, 16, 8)])
@@ -233,5 +233,5 @@ def test_dense_q_export_matches_oracle():
         m, p = mp // 2, mp % 2
         ref = oracle.dense_q(l, m, p)  # l x n_p
         n = ref.shape[1]
-        np.testing.assert_allclose(Qh[mp][:n].T, ref, atol=2e-14)
+        np.testing.assert_allclose(Qh[mp][:n].T, ref, rtol=0, atol=2e-14)
         assert np.all(Qh[mp][n:] == 0)
