@@ -191,6 +191,22 @@ def test_step2_closed_values():
         assert abs(d[0] - 1 / (2 * m + 3)) < 1e-15
 
 
+@pytest.mark.parametrize("m", [0, 1, 5, 300, 2000])
+def test_step2_coefficients_are_products_of_step1_coefficients(m):
+    # Squaring the step-one recurrence x P_k = a_{k+1} P_{k+1} + a_k P_{k-1},
+    # a_k = sqrt((k^2 - m^2) / (4k^2 - 1)), gives (recurrence0)/(recurrence) with
+    # c_l = a_{l+1} a_{l+2} and d_l = a_{l+1}^2 + a_l^2 (a_m = 0).
+    ls = np.arange(m, m + 300)
+
+    def a(k):
+        k = np.asarray(k, dtype=np.float64)
+        return np.sqrt(np.maximum(k * k - m * m, 0.0) / (4.0 * k * k - 1.0))
+
+    c, d = oracle.step2_coefficients(m, ls)
+    np.testing.assert_allclose(c, a(ls + 1) * a(ls + 2), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(d, a(ls + 1) ** 2 + a(ls) ** 2, rtol=1e-15, atol=0)
+
+
 @pytest.mark.parametrize("l", [4, 16, 40])
 def test_orthonormal_columns_all_orders(l):
     for m in range(2 * l):
