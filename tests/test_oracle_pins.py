@@ -94,6 +94,36 @@ def test_pbar_closed_forms_low_degree():
     assert np.all(P[0, :, :][[0], :] > 0)
 
 
+@pytest.mark.parametrize("m", [0, 1, 7, 120])
+def test_pbar_parity(m):
+    # Section 2.3: Pbar^m_l(-x) = (-1)^(l-m) Pbar^m_l(x).
+    x = np.linspace(0.01, 0.99, 37)
+    K = m + 400
+    Pp = oracle.pbar_orders([m], x, K)[0]
+    Pm = oracle.pbar_orders([m], -x, K)[0]
+    sign = np.where((np.arange(K + 1) - m) % 2 == 0, 1.0, -1.0)[:, None]
+    scale = np.max(np.abs(Pp), axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(Pm - sign * Pp) / scale) <= 1e-15
+
+
+def test_pbar_sturm_liouville():
+    # Lemma (sturm-liouville_Leg): -((1 - x^2) y')' + (m^2 / (1 - x^2) - l(l + 1)) y = 0, with
+    # y' and y'' from fourth-order central differences (h = 1e-3; truncation ~1e-7 here).
+    x = np.linspace(-0.8, 0.8, 17)
+    h = 1e-3
+    K = 15
+    ms = list(range(K + 1))
+    Y = {s: oracle.pbar_orders(ms, x + s * h, K) for s in (-2, -1, 0, 1, 2)}
+    d1 = (Y[-2] - 8 * Y[-1] + 8 * Y[1] - Y[2]) / (12 * h)
+    d2 = (-Y[-2] + 16 * Y[-1] - 30 * Y[0] + 16 * Y[1] - Y[2]) / (12 * h * h)
+    for m in ms:
+        for l in range(m, K + 1):
+            y = Y[0][m, l]
+            res = -(1 - x * x) * d2[m, l] + 2 * x * d1[m, l] + (m * m / (1 - x * x) - l * (l + 1)) * y
+            scale = (1 + l * (l + 1) + m * m / (1 - 0.64)) * np.max(np.abs(y))
+            assert np.max(np.abs(res)) <= 1e-6 * scale, (m, l, np.max(np.abs(res)), scale)
+
+
 def _pbar_scipy(k, m, x):
     # scipy's lpmv carries the Condon-Shortley factor (-1)^m; the paper's function does not.
     norm = math.sqrt((2 * k + 1) / 2 * math.exp(math.lgamma(k - m + 1) - math.lgamma(k + m + 1)))

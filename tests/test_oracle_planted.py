@@ -59,8 +59,17 @@ def _adjoint_without_factor_two(orig):
     return f
 
 
+def _odd_perturbation(orig):
+    # a term odd in x slipped into the recurrence (breaks the parity of Section 2.3)
+    def f(orders, x, kmax):
+        return orig(orders, x, kmax) * (1.0 + 1e-12 * np.asarray(x))[None, None, :]
+    return f
+
+
 CASES = [
     ("seed power of Pbar_m^m", "package", "pbar_orders", _seed_power, pins.test_pbar_closed_forms_low_degree),
+    ("seed power (Sturm-Liouville)", "package", "pbar_orders", _seed_power, pins.test_pbar_sturm_liouville),
+    ("term odd in x", "package", "pbar_orders", _odd_perturbation, lambda: pins.test_pbar_parity(7)),
     ("real adjoint without the factor 2", "package", "synth_adjoint", _adjoint_without_factor_two,
      lambda: pins.test_adjoint_identity("real")),
     ("phi exponent sign", "sht", "_fourier_sum", _reverse_orders, pins.test_against_scipy_spherical_harmonics),
