@@ -33,6 +33,9 @@ Readings where the paper leaves room (each is listed in the design notes):
   beta_k^{-m} = conj(beta_k^m).
 * Storage order of the coefficients: see ``coeff_index``.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 from .legendre import gauss_legendre, pbar_orders
@@ -99,12 +102,56 @@ def _chunks(seq, size):
         yield seq[s : s + size]
 
 
-def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None, orders=None):
+def _workers():
+    """Threads of the fast path: the CPUs this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _complex_times_real(A, B):
+    """A @ B for complex A and real B as two real products (the real and imaginary parts)."""
+    F = A.shape[0]
+    R = np.concatenate([A.real, A.imag], axis=0) @ B
+    return R[:F] + 1j * R[F:]
+
+
+def _for_each_order(aorders, x, kmax, fast, fn):
+    """Calls fn(m, T) with T[k - m, i] = Pbar_k^m(x_i), k = m..kmax, for every order.
+
+    Default: numpy tables (``pbar_orders``) for chunks of orders, in order.  fast=True: the
+    same functions from the C routine of ``pbar_c`` (same recurrence), one order per task
+    on a pool of threads (orders are independent; each task writes only its own order's
+    outputs, and the products inside a task run single-threaded).
+    """
+    if not fast:
+        chunk = max(1, min(len(aorders), (1 << 24) // max(1, (kmax + 1) * len(x))))
+        for ms in _chunks(aorders, chunk):
+            P = pbar_orders(ms, x, kmax)
+            for a, m in enumerate(ms):
+                fn(m, P[a, m:, :])
+        return
+    from threadpoolctl import threadpool_limits
+
+    from .pbar_c import pbar_table_c
+
+    def task(m):
+        fn(m, pbar_table_c(m, x, kmax))
+
+    with threadpool_limits(1), ThreadPoolExecutor(_workers()) as ex:
+        for _ in ex.map(task, list(aorders)):
+            pass
+
+
+def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None, orders=None, fast=False):
     """g[f, m + 2l - 1, i] = sum_k beta_k^m Pbar_k^{|m|}(x_i) for all m.
 
     For real fields the negative orders are filled in by conjugation.  With
     ``orders`` (a list of |m|) only those orders are summed; the others stay 0,
-    i.e. the coefficients of the other orders are treated as zero.
+    i.e. the coefficients of the other orders are treated as zero.  ``fast`` takes the
+    tables from the C routine on a pool of threads (see ``_for_each_order``).
     """
     beta = np.atleast_2d(np.asarray(beta, dtype=np.complex128))
     F = beta.shape[0]
@@ -112,19 +159,23 @@ def legendre_sums(beta, l, x, kind="complex", orders_per_chunk=None, orders=None
     N = len(x)
     L2 = 2 * l
     g = np.zeros((F, 2 * L2 - 1, N), dtype=np.complex128)
-    if orders_per_chunk is None:
-        orders_per_chunk = max(1, min(L2, (1 << 24) // max(1, L2 * N)))
     aorders = list(range(L2)) if orders is None else sorted({abs(int(m)) for m in orders})
-    for ms in _chunks(aorders, orders_per_chunk):
-        P = pbar_orders(ms, x, L2 - 1)
-        for a, m in enumerate(ms):
-            Pm = P[a, m:, :]  # (degrees, nodes)
-            g[:, m + L2 - 1, :] = beta[:, _order_slice(l, m, kind)] @ Pm
-            if m > 0:
-                if kind == "complex":
-                    g[:, -m + L2 - 1, :] = beta[:, _order_slice(l, -m, kind)] @ Pm
-                else:
-                    g[:, -m + L2 - 1, :] = np.conj(g[:, m + L2 - 1, :])
+
+    def one(m, Pm):  # Pm: (degrees, nodes)
+        g[:, m + L2 - 1, :] = _complex_times_real(beta[:, _order_slice(l, m, kind)], Pm)
+        if m > 0:
+            if kind == "complex":
+                g[:, -m + L2 - 1, :] = _complex_times_real(beta[:, _order_slice(l, -m, kind)], Pm)
+            else:
+                g[:, -m + L2 - 1, :] = np.conj(g[:, m + L2 - 1, :])
+
+    if orders_per_chunk is not None and not fast:
+        for ms in _chunks(aorders, orders_per_chunk):
+            P = pbar_orders(ms, x, L2 - 1)
+            for a, m in enumerate(ms):
+                one(m, P[a, m:, :])
+    else:
+        _for_each_order(aorders, x, L2 - 1, fast, one)
     return g
 
 
@@ -161,13 +212,14 @@ def _fourier_coeffs(f, l, grid, direct, normalize):
     return G
 
 
-def synth(beta, l, kind="complex", grid="fft", direct=False, orders=None):
+def synth(beta, l, kind="complex", grid="fft", direct=False, orders=None, fast=False):
     """Grid values f[field, ring, j] from coefficients beta[field, :] (canonical order).
 
-    ``orders`` restricts the expansion to the listed |m| (other orders taken as zero).
+    ``orders`` restricts the expansion to the listed |m| (other orders taken as zero);
+    ``fast`` takes the Legendre tables from the C routine on a pool of threads.
     """
     x, _ = gauss_legendre(2 * l)
-    g = legendre_sums(beta, l, x, kind, orders=orders)
+    g = legendre_sums(beta, l, x, kind, orders=orders, fast=fast)
     f = _fourier_sum(g, l, grid, direct)
     return f.real.copy() if kind == "real" else f
 
@@ -180,50 +232,50 @@ def ring_values(beta, l, rings, kind="complex", grid="fft", direct=False):
     return f.real.copy() if kind == "real" else f
 
 
-def _coefficient_sums(G, l, weights, x, kind, orders=None):
+def _coefficient_sums(G, l, weights, x, kind, orders=None, fast=False):
     """beta_k^m = sum_i weights_i Pbar_k^{|m|}(x_i) G[f, m, i] for the orders asked."""
     F = G.shape[0]
     L2 = 2 * l
     out = np.zeros((F, n_coeffs(l, kind)), dtype=np.complex128)
     aorders = list(range(L2)) if orders is None else sorted({abs(int(m)) for m in orders})
-    chunk = max(1, min(L2, (1 << 24) // max(1, L2 * len(x))))
-    for ms in _chunks(aorders, chunk):
-        P = pbar_orders(ms, x, L2 - 1)
-        for a, m in enumerate(ms):
-            PW = P[a, m:, :] * weights[None, :]  # (degrees, nodes)
-            out[:, _order_slice(l, m, kind)] = G[:, m + L2 - 1, :] @ PW.T
-            if m > 0 and kind == "complex":
-                out[:, _order_slice(l, -m, kind)] = G[:, -m + L2 - 1, :] @ PW.T
+
+    def one(m, Pm):
+        PWT = (Pm * weights[None, :]).T  # (nodes, degrees), a transposed view
+        out[:, _order_slice(l, m, kind)] = _complex_times_real(G[:, m + L2 - 1, :], PWT)
+        if m > 0 and kind == "complex":
+            out[:, _order_slice(l, -m, kind)] = _complex_times_real(G[:, -m + L2 - 1, :], PWT)
+
+    _for_each_order(aorders, x, L2 - 1, fast, one)
     return out
 
 
-def analyze(f, l, kind="complex", grid="fft", direct=False):
+def analyze(f, l, kind="complex", grid="fft", direct=False, fast=False):
     """Coefficients (canonical order) from grid values f[field, ring, j]."""
     f = np.asarray(f)
     if f.ndim == 2:
         f = f[None]
     x, w = gauss_legendre(2 * l)
     G = _fourier_coeffs(f.astype(np.complex128), l, grid, direct, normalize=True)
-    out = _coefficient_sums(G, l, w, x, kind)
+    out = _coefficient_sums(G, l, w, x, kind, fast=fast)
     if kind == "real":
         out[:, : 2 * l] = out[:, : 2 * l].real
     return out
 
 
-def analyze_orders(f, l, orders, kind="complex", grid="fft"):
+def analyze_orders(f, l, orders, kind="complex", grid="fft", fast=False):
     """Analysis for a subset of orders; entries of other orders are left at zero."""
     f = np.asarray(f)
     if f.ndim == 2:
         f = f[None]
     x, w = gauss_legendre(2 * l)
     G = _fourier_coeffs(f.astype(np.complex128), l, grid, False, normalize=True)
-    out = _coefficient_sums(G, l, w, x, kind, orders)
+    out = _coefficient_sums(G, l, w, x, kind, orders, fast=fast)
     if kind == "real":
         out[:, : 2 * l] = out[:, : 2 * l].real
     return out
 
 
-def synth_adjoint(r, l, kind="complex", grid="fft", direct=False, orders=None):
+def synth_adjoint(r, l, kind="complex", grid="fft", direct=False, orders=None, fast=False):
     """Adjoint of ``synth`` for the real inner products of its input and output.
 
     Complex fields: gamma_k^m = sum_i Pbar_k^{|m|}(x_i) sum_j r_ij e^{-i m phi_j}
@@ -236,7 +288,7 @@ def synth_adjoint(r, l, kind="complex", grid="fft", direct=False, orders=None):
         r = r[None]
     x, _ = gauss_legendre(2 * l)
     G = _fourier_coeffs(r.astype(np.complex128), l, grid, direct, normalize=False)
-    out = _coefficient_sums(G, l, np.ones_like(x), x, kind, orders)
+    out = _coefficient_sums(G, l, np.ones_like(x), x, kind, orders, fast=fast)
     if kind == "real":
         out *= 2.0
         out[:, : 2 * l] = 0.5 * out[:, : 2 * l].real

@@ -51,8 +51,8 @@ def _seed_power(orig):
 
 def _adjoint_without_factor_two(orig):
     # the real-field adjoint without its factor 2 on the m > 0 orders
-    def f(r, l, kind="complex", grid="fft", direct=False, orders=None):
-        out = orig(r, l, kind, grid, direct, orders)
+    def f(r, l, kind="complex", grid="fft", direct=False, orders=None, **kw):
+        out = orig(r, l, kind, grid, direct, orders, **kw)
         if kind == "real":
             out[:, 2 * l:] *= 0.5
         return out
