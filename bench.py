@@ -2,20 +2,21 @@
 
 One step = synthesis of a batch of F fields (coefficients -> 2l x 4l grid) followed by
 analysis of that grid back to coefficients, on one MI355X, with every input already in
-device memory.  value = F * steps / (timed seconds) for the split-FP32 butterfly (the
---precision default); the plain FP64 butterfly and plain FP32 are timed the same way in the
-same run and reported under "variants", with the per-field relative l2 error of each
-variant against the FP64 butterfly on the full batch ("err_vs_fp64").  The plan precompute
-is excluded and reported as t_plan_s.
+device memory.  value = F / (median step time) for the split-FP32 butterfly (the
+--precision default), timed with per-launch profiling off; the plain FP64 butterfly and plain
+FP32 are timed the same way in the same run and reported under "variants", with the
+per-field relative l2 error of each variant against the FP64 butterfly on the full batch
+("err_vs_fp64").  The plan precompute is excluded and reported as t_plan_s.
 
 The JSON line also carries
- * roofline: the stage with the largest share of the timed kernel time, its algorithmic
-   flops (factor entries x R x 2) or bytes per launch divided by its mean launch time as
-   measured with HIP events inside the library on the launch stream, against the MI355X
-   peak of the unit that bounds it;
- * cpu_baseline: the CPU oracle timed on a bounded sample of the same workload (a subset
-   of orders, a subset of fields), extrapolated by the exact operation counts, with the
-   GPU-vs-oracle error on that sample.
+ * roofline: the kernel launch with the largest share of a profiled pass over the same steps
+   (every launch bracketed by HIP events on its stream), its FP64-equivalent algorithmic flops
+   (2 x factor entries x R) over its mean launch time against the dense matrix-core peak of
+   the unit the form runs on; step_roofline gives the same for the whole step;
+ * cpu_baseline: the CPU oracle timed on the host cores over a few whole fields (every order,
+   synthesis then analysis), with the GPU-vs-oracle error of every precision on those fields;
+ * gate: the split form's 1e-9 bound per field and direction against the oracle (the run
+   exits with status 1 when it fails).
 """
 import argparse
 import json
@@ -46,10 +47,8 @@ def parse():
     ap.add_argument("--leaf-width", type=int, default=64)
     ap.add_argument("--eps", type=float, default=1e-12)
     ap.add_argument("--power", type=float, default=1.5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-orders", type=int, default=48)
-    ap.add_argument("--cpu-fields", type=int, default=4,
-                    help="fields in the oracle sample (a multiple of 4 for the matrix-core variants)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle check of whole fields (and with it the CPU baseline and the gate)")
     ap.add_argument("--workload", default="metric", choices=["metric", "mixed", "single"],
                     help="metric: the l=1024, 64-field line; mixed: 96 requests of mixed bandlimits "
                          "through the batched persistent launch, beside one call per request; single: "
@@ -73,8 +72,17 @@ def rel_err_per_field(a, b):
     return (torch.linalg.norm(d, dim=1) / torch.linalg.norm(r, dim=1)).cpu().numpy()
 
 
-def cpu_baseline(plan, args, beta_np, grid_seed_np):
-    """Time the oracle on a sample of orders and fields; extrapolate to the full batch."""
+ORACLE_FIELDS = (0, 21, 42, 63)  # fields of the full-order oracle check (spread over the batch)
+
+
+def oracle_check(plan, args, beta_np):
+    """Full-order oracle check of a few fields, which is also the CPU baseline's measurement.
+
+    The oracle synthesises the chosen fields from their coefficients over every order and
+    analyses its own grid back (both timed on the host cores: that time is the CPU
+    baseline); the GPU runs the same two transforms, at the benchmark's launch
+    configuration (the fields sit in a batch of F), in every precision timed here, and its
+    output is compared field by field with the oracle's (relative l2, all orders)."""
     import numpy as np
     import torch
     from threadpoolctl import threadpool_info
@@ -82,55 +90,38 @@ def cpu_baseline(plan, args, beta_np, grid_seed_np):
     import oracle
 
     l, F = args.l, args.fields
-    L2 = 2 * l
-    Fs = min(args.cpu_fields, F)
-    norders = max(2, min(args.cpu_orders, L2))
-    sample = sorted(set(int(round(v)) for v in np.linspace(0, L2 - 1, norders)))
-    ms = np.abs(__import__("sht_synthetic").orders_canonical(l))
-    mask = np.isin(ms, sample)
-    beta_s = np.where(mask[None, :], beta_np[:Fs], 0.0)
-
-    # oracle: synthesis and analysis of the sampled orders (Legendre sums) ...
+    fo = sorted({f for f in ORACLE_FIELDS if f < F}) or [0]
     t0 = time.perf_counter()
-    f_ref = oracle.synth(beta_s, l, orders=sample)
+    f_ref = oracle.synth(beta_np[fo], l, fast=True)
     t1 = time.perf_counter()
-    a_ref = oracle.analyze_orders(grid_seed_np[:Fs], l, sample)
+    a_ref = oracle.analyze(f_ref, l, fast=True)
     t2 = time.perf_counter()
-    # ... and the longitude FFTs of the sampled fields (both directions)
-    g = np.fft.ifft(f_ref, axis=-1)
-    g = np.fft.fft(g, axis=-1)
-    t3 = time.perf_counter()
-    # Legendre cost of an order is proportional to its degree count 2l - |m| (both signs)
-    w_all = sum((L2 - m) * (1 if m == 0 else 2) for m in range(L2))
-    w_s = sum((L2 - m) * (1 if m == 0 else 2) for m in sample)
-    # synth() and analyze_orders() each include one FFT pass over Fs fields; remove it
-    t_fft_pair = t3 - t2
-    t_leg = max(1e-9, (t1 - t0) + (t2 - t1) - t_fft_pair)
-    t_full = (t_leg * w_all / w_s + t_fft_pair) * (F / Fs)
+    cores = oracle.sht._workers()
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [cores])
 
-    # GPU on the same sampled inputs (outside the timed region), every variant
-    dev_b = torch.from_numpy(np.ascontiguousarray(beta_s)).to("cuda")
-    dev_g = torch.from_numpy(np.ascontiguousarray(grid_seed_np[:Fs])).to("cuda")
-    a_ref = a_ref[:, mask]
+    dev_b = torch.from_numpy(np.ascontiguousarray(beta_np)).to("cuda")
+    g_in = torch.zeros((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
+    g_in[fo] = torch.from_numpy(f_ref).to("cuda")
     errs = {}
-    for prec in dict.fromkeys([args.precision, "fp64"]):
-        f_gpu = plan.synth(dev_b, precision=prec).cpu().numpy()
-        a_gpu = plan.analyze(dev_g, precision=prec).cpu().numpy()[:, mask]
+    for prec in dict.fromkeys([args.precision, "fp64"] + ([] if args.no_variants else ["split32"])):
+        f_gpu = plan.synth(dev_b, precision=prec)[fo].cpu().numpy()
+        a_gpu = plan.analyze(g_in, precision=prec)[fo].cpu().numpy()
         errs[prec] = {
-            "synth": [float(np.linalg.norm(f_gpu[i] - f_ref[i]) / np.linalg.norm(f_ref[i])) for i in range(Fs)],
+            "synth": [float(np.linalg.norm(f_gpu[i] - f_ref[i]) / np.linalg.norm(f_ref[i])) for i in range(len(fo))],
             "analysis": [float(np.linalg.norm(a_gpu[i] - a_ref[i]) / np.linalg.norm(a_ref[i]))
-                         for i in range(Fs)],
+                         for i in range(len(fo))],
         }
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    return {
-        "value": F / t_full,
+    del dev_b, g_in
+    torch.cuda.empty_cache()
+    baseline = {
+        "value": len(fo) / (t2 - t0),
         "unit": "pairs/s",
-        "cores": int(threads),
+        "cores": int(min(threads, cores)),
         "kind": "oracle",
-        "sample": f"{len(sample)} of {L2} orders ({sample[0]}..{sample[-1]}), {Fs} of {F} fields; "
-                  f"measured {t3 - t0:.1f} s, extrapolated by degree counts to {t_full:.0f} s per batch",
-        "gpu_rel_err_vs_oracle": errs,
+        "sample": f"{len(fo)} of {F} fields (fields {fo}), every order |m| = 0..{2 * l - 1}: synthesis then "
+                  f"analysis of its grid, measured {t1 - t0:.1f} s + {t2 - t1:.1f} s (not extrapolated)",
     }
+    return baseline, {"fields": fo, "rel_l2": errs}
 
 
 def time_pairs(plan, prec, beta, grid, back, steps, warmup, profile=False):
@@ -310,23 +301,60 @@ def measured_traffic(launch):
     return ent["bytes"]
 
 
-def roofline(prof, ms_total, precision):
-    """The single kernel launch with the largest share of the timed kernel time."""
+PRODUCTS = {"fp64": 1, "split32": 4, "fp32": 1}  # MFMA products per FP64-equivalent product
+
+
+def grid_bytes(l, F):
+    return float(F) * 2 * l * 4 * l * 16
+
+
+def roofline(prof, precision, l, F):
+    """The single kernel launch with the largest share of the timed kernel time.
+
+    A Legendre launch (levels, finals) at many fields is a dense contraction, bound by the
+    matrix cores: achieved = its FP64-equivalent algorithmic flops (2 x factor entries x R)
+    over its mean launch time, against the dense peak of the unit the form runs on (FP64
+    MFMA for fp64, FP32 MFMA for split32 / fp32); executed flops (products per FP64-
+    equivalent product) are given beside it.  An FFT launch is bound by HBM: achieved = its
+    grid bytes (read or written once) over its mean launch time; the m <-> ring intermediate
+    it also moves is not algorithmic and is reported separately."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     mean_s = rec["ms"] / rec["launches"] / 1e3
-    flops_rate = rec["flops"] / mean_s
-    bytes_rate = rec["bytes"] / mean_s
     peak_f = PEAK["fp64"] if precision == "fp64" else PEAK["fp32"]
-    if rec["flops"] > 0 and rec["flops"] / max(rec["bytes"], 1.0) > peak_f / PEAK["hbm"]:
-        roof = {"bound": "mfma", "achieved": flops_rate / 1e12, "peak": peak_f / 1e12,
-                "unit": "TFLOP/s", "frac": flops_rate / peak_f}
+    if ".fft/" not in name:
+        roof = {"bound": "mfma", "achieved": rec["flops"] / mean_s / 1e12, "peak": peak_f / 1e12,
+                "unit": "TFLOP/s", "frac": rec["flops"] / mean_s / peak_f,
+                "flops_per_launch": rec["flops"],
+                "executed_flops_per_launch": rec["flops"] * PRODUCTS[precision],
+                "executed_frac": rec["flops"] * PRODUCTS[precision] / mean_s / peak_f,
+                "nonalgorithmic_bytes_per_launch": rec["bytes"],
+                "nonalgorithmic_note": "factor words plus the butterfly vector / m<->ring rows the launch "
+                                       "reads and writes (HBM traffic of this layout, not of the method)"}
     else:
-        roof = {"bound": "hbm", "achieved": bytes_rate / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": bytes_rate / PEAK["hbm"]}
+        gb = grid_bytes(l, F)
+        roof = {"bound": "hbm", "achieved": gb / mean_s / 1e9, "peak": PEAK["hbm"] / 1e9, "unit": "GB/s",
+                "frac": gb / mean_s / PEAK["hbm"], "bytes_per_launch": gb,
+                "nonalgorithmic_bytes_per_launch": rec["bytes"] - gb}
     roof.update({"kernel": name, "mean_launch_ms": mean_s * 1e3, "launches": rec["launches"],
-                 "flops_per_launch": rec["flops"], "bytes_per_launch": rec["bytes"],
-                 "traffic": measured_traffic(name), "share_of_step": rec["ms"] / ms_total})
+                 "traffic": measured_traffic(name)})
     return roof
+
+
+def step_roofline(prof, steps, ms_step, precision, l, F, fac_entries):
+    """Whole step: FP64-equivalent flops of every launch of a step over the step time, and the
+    algorithmic HBM bytes of the method (factors read once per direction, coefficients and
+    grid each read or written once per direction)."""
+    flops = sum(v["flops"] * v["launches"] for v in prof.values()) / steps
+    peak_f = PEAK["fp64"] if precision == "fp64" else PEAK["fp32"]
+    coef_bytes = float(F) * 4 * l * l * 16
+    fac_bytes = 2.0 * fac_entries * 8
+    algo_bytes = fac_bytes + 2 * coef_bytes + 2 * grid_bytes(l, F)
+    layout_bytes = sum(v["bytes"] * v["launches"] for v in prof.values()) / steps
+    s = ms_step / 1e3
+    return {"flops_per_step": flops, "tflops": flops / s / 1e12, "mfma_peak_tflops": peak_f / 1e12,
+            "mfma_frac": flops / s / peak_f, "executed_mfma_frac": flops * PRODUCTS[precision] / s / peak_f,
+            "algorithmic_bytes_per_step": algo_bytes, "hbm_frac_algorithmic": algo_bytes / s / PEAK["hbm"],
+            "layout_bytes_per_step": layout_bytes}
 
 
 def mixed(args):
@@ -414,6 +442,9 @@ def mixed(args):
     print(json.dumps(out), flush=True)
 
 
+GATE = 1e-9  # relative l2 per field and direction against the oracle (split-FP32)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -424,10 +455,9 @@ def main():
         return mixed(args)
     metric = METRIC
     if args.workload == "single":
-        # one complex field, l = 256, FP64 butterfly (vector kernels at R = 4): the oracle runs
-        # on every order
+        # one complex field, l = 256, FP64 butterfly (vector kernels at R = 4)
         args.l, args.fields, args.precision, args.no_variants = 256, 1, "fp64", True
-        args.power, args.eps, args.cpu_fields, args.cpu_orders = 1.0, 1e-13, 1, 512
+        args.power, args.eps = 1.0, 1e-13
         metric = "SHT synth+analysis pairs/s at l=256, 1 field, FP64 butterfly"
     import numpy as np
     import torch
@@ -452,46 +482,54 @@ def main():
     print(f"# plan l={l} eps={args.eps} C={args.leaf_width}: {t_plan:.1f} s, k_max={st['k_max']} "
           f"k_avg={st['k_avg']:.1f} factors={st['factor_entries']:.3e} (columns {st['t_columns_s']:.1f} s, "
           f"IDs {st['t_compress_s']:.1f} s)", file=sys.stderr, flush=True)
+    precs = [args.precision] if args.no_variants else list(dict.fromkeys([args.precision, "fp64", "split32", "fp32"]))
+    for prec in precs:
+        plan.prepare(prec)
 
     beta_np = syn.coefficients(l, F, seed=0, power=args.power)
     beta = torch.from_numpy(beta_np).to("cuda")
     grid = torch.empty((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
     back = torch.empty_like(beta)
 
-    ms_total, per_step, wall, prof = time_pairs(plan, args.precision, beta, grid, back, args.steps,
-                                                args.warmup, profile=True)
-    ms_step = ms_total / args.steps
-    value = F * args.steps / (ms_total / 1e3)
+    # headline: per-launch profiling off, median of the per-step times
+    ms_total, per_step, wall, _ = time_pairs(plan, args.precision, beta, grid, back, args.steps, args.warmup)
+    ms_step = float(np.median(per_step))
+    value = F / (ms_step / 1e3)
     err_rt = rel_err_per_field(back, beta)
-    print(f"# {args.precision}: {value:.1f} pairs/s, {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+    print(f"# {args.precision}: {value:.1f} pairs/s, median {ms_step:.2f} ms/step (mean {ms_total / args.steps:.2f})",
+          file=sys.stderr, flush=True)
+    # the same steps again with every launch bracketed by HIP events on its stream
+    ms_prof, _, _, prof = time_pairs(plan, args.precision, beta, grid, back, args.steps, 1, profile=True)
 
     variants = {}
-    if not args.no_variants:
-        for prec in ("fp64", "split32", "fp32"):
-            if prec == args.precision:
-                continue
-            ms_v, per_v, _, prof_v = time_pairs(plan, prec, beta, grid, back, args.steps, args.warmup,
-                                                profile=prec == "fp64")
-            variants[prec] = {"value": F * args.steps / (ms_v / 1e3), "ms_per_step": ms_v / args.steps,
-                              "ms_per_step_median": float(np.median(per_v))}
-            if prof_v:
-                variants[prec]["stages_ms_per_step"] = stage_totals(prof_v, args.steps)
-            print(f"# {prec}: {variants[prec]['value']:.1f} pairs/s", file=sys.stderr, flush=True)
-        if args.per_field_steps > 0:
-            ms_pf = time_per_field(plan, beta, args.per_field_steps)
-            variants["fp64_per_field"] = {"value": F * args.per_field_steps / (ms_pf / 1e3),
-                                          "ms_per_step": ms_pf / args.per_field_steps,
-                                          "note": f"{F} single-field calls per direction per step"}
-            print(f"# fp64 per field: {variants['fp64_per_field']['value']:.1f} pairs/s", file=sys.stderr,
-                  flush=True)
+    stages64 = None
+    for prec in precs:
+        if prec == args.precision:
+            continue
+        ms_v, per_v, _, _ = time_pairs(plan, prec, beta, grid, back, args.steps, args.warmup)
+        med = float(np.median(per_v))
+        variants[prec] = {"value": F / (med / 1e3), "ms_per_step": med, "ms_per_step_mean": ms_v / args.steps}
+        if prec == "fp64":
+            _, _, _, prof_v = time_pairs(plan, prec, beta, grid, back, args.steps, 1, profile=True)
+            variants[prec]["stages_ms_per_step"] = stages64 = stage_totals(prof_v, args.steps)
+            variants[prec]["roofline"] = roofline(prof_v, prec, l, F)
+        print(f"# {prec}: {variants[prec]['value']:.1f} pairs/s", file=sys.stderr, flush=True)
+    if not args.no_variants and args.per_field_steps > 0:
+        ms_pf = time_per_field(plan, beta, args.per_field_steps)
+        variants["fp64_per_field"] = {"value": F * args.per_field_steps / (ms_pf / 1e3),
+                                      "ms_per_step": ms_pf / args.per_field_steps,
+                                      "note": f"{F} single-field calls per direction per step"}
+        print(f"# fp64 per field: {variants['fp64_per_field']['value']:.1f} pairs/s", file=sys.stderr,
+              flush=True)
+    if args.precision == "fp64":
+        stages64 = stage_totals(prof, args.steps)
 
     gemm = None
-    if not args.no_gemm_baseline and ("fp64" in variants or args.precision == "fp64"):
+    if not args.no_gemm_baseline and stages64 is not None and F > 1:
         gemm = gemm_baseline(plan, l, 4 * F, max(2, min(args.steps, 5)))
-        st64 = variants["fp64"]["stages_ms_per_step"] if "fp64" in variants else stage_totals(prof, args.steps)
-        bf = {d: sum(v for k, v in st64.items() if k.startswith(d + ".") and ".fft/" not in k)
+        bf = {d: sum(v for k, v in stages64.items() if k.startswith(d + ".") and ".fft/" not in k)
               for d in ("synth", "analysis")}
-        fft = sum(v for k, v in st64.items() if ".fft/" in k)
+        fft = sum(v for k, v in stages64.items() if ".fft/" in k)
         gemm["butterfly_fp64_legendre_ms"] = bf
         gemm["pairs_per_s_with_fft"] = F / ((gemm["synth_ms"] + gemm["analysis_ms"] + fft) / 1e3)
         print(f"# dense DGEMM Legendre: synth {gemm['synth_ms']:.1f} ms, analysis {gemm['analysis_ms']:.1f} ms "
@@ -507,7 +545,7 @@ def main():
     err64 = {}
     g64 = plan.synth(beta, precision="fp64")
     b64 = plan.analyze(g64, precision="fp64")
-    for prec in ([args.precision] if args.no_variants else ["split32", "fp32"]):
+    for prec in precs:
         if prec == "fp64":
             continue
         es = rel_err_per_field(plan.synth(beta, out=grid, precision=prec), g64)
@@ -525,17 +563,19 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step_mean": ms_total / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "split32": "f32", "fp32": "f32"}[args.precision],
+        "dtype": {"fp64": "f64", "split32": "f32-split (FP32 MFMA products, f64 accumulation)",
+                  "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"SHT synthesis+analysis, l={l} (degrees 0..{2 * l - 1}), {F} complex "
                                f"fields, grid {2 * l}x{4 * l}, coefficients CN(0,1)/(1+k)^{args.power}",
                    "l": l, "fields": F, "precision": args.precision, "leaf_width": args.leaf_width,
                    "eps": args.eps},
-        "roofline": roofline(prof, ms_total, args.precision),
+        "roofline": roofline(prof, args.precision, l, F),
+        "step_roofline": step_roofline(prof, args.steps, ms_step, args.precision, l, F, st["factor_entries"]),
         "variants": variants,
         "dense_gemm_fp64": gemm,
         "err_vs_fp64": err64,
@@ -545,13 +585,29 @@ def main():
                                     "m_max_words", "device_bytes", "t_columns_s", "t_compress_s",
                                     "max_abs_t")},
         "wall_s_timed": wall,
+        "profiled_ms_per_step": ms_prof / args.steps,
         "stages_ms_per_step": stage_totals(prof, args.steps),
         "launches_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},
     }
+    gate_ok = True
     if not args.no_cpu_baseline:
-        grid_seed = syn.grid(l, min(args.cpu_fields, F), seed=1)
-        out["cpu_baseline"] = cpu_baseline(plan, args, beta_np, grid_seed)
+        out["cpu_baseline"], chk = oracle_check(plan, args, beta_np)
+        out["oracle_check"] = chk
+        # gate: every checked field in both directions within GATE of the oracle, and every
+        # field of the batch within GATE once its distance to the FP64 butterfly is added to the
+        # FP64 butterfly's own largest distance to the oracle
+        tol = {"fp64": 1e-11, "split32": GATE, "fp32": 1e-4}
+        e64 = max(max(chk["rel_l2"]["fp64"]["synth"]), max(chk["rel_l2"]["fp64"]["analysis"]))
+        bound = {p: max(v["synth_max"], v["analysis_max"]) + e64 for p, v in err64.items()}
+        checked = {p: max(max(v["synth"]), max(v["analysis"])) for p, v in chk["rel_l2"].items()}
+        gate_ok = all(checked[p] <= tol[p] for p in checked) and all(bound[p] <= tol[p] for p in bound)
+        out["gate"] = {"tolerance": tol, "oracle_checked_max": checked, "all_fields_bound": bound,
+                       "pass": gate_ok}
+        print(f"# gate {'pass' if gate_ok else 'FAIL'}: oracle (fields {chk['fields']}, all orders) {checked}; "
+              f"all-field bound {bound}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
+    if not gate_ok:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -11,6 +11,7 @@ SHT_ENOMEM = -2
 SHT_EHIP = -3
 SHT_EUNSUPPORTED = -4
 SHT_EINTERNAL = -5
+SHT_ENOTREADY = -6
 
 SHT_FP64 = 0
 SHT_SPLIT32 = 1
@@ -31,6 +32,7 @@ class PlanOpts(ctypes.Structure):
         ("field_kind", ctypes.c_int),
         ("host_threads", ctypes.c_int),
         ("device", ctypes.c_int),
+        ("split_only", ctypes.c_int),
     ]
 
 
@@ -106,6 +108,7 @@ SIGNATURES = {
     "sht_plan": (_I, [_I, _D, ctypes.POINTER(_P)]),
     "sht_plan_ex": (_I, [_I, _D, ctypes.POINTER(PlanOpts), ctypes.POINTER(_P)]),
     "sht_destroy": (None, [_P]),
+    "sht_plan_prepare": (_I, [_P, _I, _P]),
     "sht_workspace_bytes": (_S, [_P, _I, _I]),
     "sht_synth": (_I, [_P, _P, _P, _I, _P, _S, _P]),
     "sht_analyze": (_I, [_P, _P, _P, _I, _P, _S, _P]),

@@ -121,10 +121,11 @@ int check_call(const sht_plan_s* P, int precision, const void* a, const void* b,
                size_t wsb) {
   if (!P || !a || !b || F < 1 || !ws) return SHT_EINVAL;
   if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
-  // the split and FP32 variants run on the matrix-core kernels only (R a multiple of 16), and
-  // the transposed final stage keeps at most 384 skeleton rows per task in registers
-  if (precision != SHT_FP64 && (!mfma_ok(field_width(P, F)) || P->final_maxk > 192))
-    return SHT_EUNSUPPORTED;
+  // the split and FP32 variants run on the matrix-core kernels only (R a multiple of 16), on
+  // factor copies that sht_plan_prepare (or a plan built for that precision) derived
+  if (precision != SHT_FP64 && !mfma_ok(field_width(P, F))) return SHT_EUNSUPPORTED;
+  if (precision != SHT_FP64 && !P->d.fac_hl) return SHT_ENOTREADY;
+  if (precision == SHT_FP64 && !P->d.fac) return SHT_ENOTREADY;  // a split-only plan
   if (reinterpret_cast<uintptr_t>(a) % 16 || reinterpret_cast<uintptr_t>(b) % 16) return SHT_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return SHT_EINVAL;
   if (wsb < ws_bytes(P, F)) return SHT_EINVAL;
@@ -204,7 +205,6 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const std::string fs = fsuffix(F, precision);
@@ -257,7 +257,6 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   DeviceScope ds(P->device);
   if (!ds.ok()) return SHT_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) return SHT_EHIP;
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);
@@ -305,6 +304,7 @@ void sht_default_opts(sht_plan_opts* o) {
   o->field_kind = SHT_COMPLEX;
   o->host_threads = 0;
   o->device = -1;
+  o->split_only = 0;
 }
 
 int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nullptr, out); }
@@ -320,6 +320,7 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
     return SHT_EINVAL;
   if (o.precision < SHT_FP64 || o.precision > SHT_FP32) return SHT_EINVAL;
   if (o.field_kind != SHT_COMPLEX && o.field_kind != SHT_REAL) return SHT_EINVAL;
+  if (o.split_only && o.precision == SHT_FP64) return SHT_EINVAL;
   if (!pow2(l) || l > 2048) return SHT_EUNSUPPORTED;
   int dev = o.device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return SHT_EHIP;
@@ -341,6 +342,15 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   } catch (...) {
     rc = SHT_EINTERNAL;
   }
+  // a plan built for a split or FP32 default derives those factor copies now, so that its
+  // transforms never allocate or wait
+  if (rc == SHT_OK && P->precision != SHT_FP64 && split_factors(P, nullptr) != hipSuccess) rc = SHT_EHIP;
+  if (rc == SHT_OK && o.split_only) {
+    (void)hipFree(P->d.fac);
+    (void)hipFree(P->d.fac_t);
+    P->d.fac = P->d.fac_t = nullptr;
+    P->stats.device_bytes -= static_cast<long long>(2 * P->n_fac * sizeof(double));
+  }
   if (rc != SHT_OK) {
     free_plan_device(P);
     delete P;
@@ -348,6 +358,17 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   }
   *out = P;
   return SHT_OK;
+}
+
+int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
+  if (!plan) return SHT_EINVAL;
+  if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
+  if (precision == SHT_FP64) return plan->d.fac ? SHT_OK : SHT_ENOTREADY;
+  DeviceScope ds(plan->device);
+  if (!ds.ok()) return SHT_EHIP;
+  const hipError_t e = ensure_split_factors(plan, static_cast<hipStream_t>(stream));
+  if (e == hipErrorOutOfMemory) return SHT_ENOMEM;
+  return e == hipSuccess ? SHT_OK : SHT_EHIP;
 }
 
 void sht_destroy(sht_plan_t plan) {
@@ -667,6 +688,7 @@ const char* sht_strerror(int status) {
     case SHT_EHIP: return "HIP runtime error";
     case SHT_EUNSUPPORTED: return "unsupported configuration";
     case SHT_EINTERNAL: return "internal error";
+    case SHT_ENOTREADY: return "plan not prepared for this precision (sht_plan_prepare)";
     default: return "unknown status";
   }
 }

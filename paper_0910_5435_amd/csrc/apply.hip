@@ -336,8 +336,7 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
                         double* v0w, double* v1w, double* y, const double* yin, int R,
                         int precision, bool adjoint, hipStream_t s, int cls) {
   if (P->n_final == 0) return hipSuccess;
-  // the transposed MFMA kernel keeps at most 24 row tiles (k0 + k1 <= 384) in registers
-  if (mfma_ok(R) && (!transpose || P->final_maxk <= 192))
+  if (mfma_ok(R))
     return launch_final_mfma(P, transpose, v0, v1, v0w, v1w, y, yin, R, precision, adjoint, s, cls);
   if (precision != SHT_FP64) return hipErrorNotSupported;
   const int RT = pick_rt(R, std::max(2LL * P->final_maxk, 64LL * 2));

@@ -746,7 +746,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
                                  int l, int R, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  constexpr int MAXT = 6;  // row tiles per wave (k0 + k1 <= 384)
+  constexpr int MAXT = 6;  // row tiles per wave and pass: a pass covers 4 MAXT tiles (384 rows)
   double* eo[2] = {lds, lds + ICH * LD};
   __shared__ double red_s[256];
   __shared__ int colsc[2][NT];
@@ -758,6 +758,9 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
+  // Output tiles [0, nm0 + nm1) are covered in passes of 4 MAXT tiles (the accumulators one
+  // wave keeps in registers); ranks k0 + k1 above 384 take more than one pass over the rows.
+  for (int t0 = 0; t0 < nm0 + nm1; t0 += 4 * MAXT) {
   Acc<PREC> acc[MAXT][NTL];
 #pragma unroll
   for (int u = 0; u < MAXT; ++u)
@@ -789,7 +792,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
     }
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
-      const int q = wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
+      const int q = t0 + wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
       if (q >= nm0 + nm1) break;
       const int p = q < nm0 ? 0 : 1;
       const int k = p ? k1 : k0;
@@ -832,7 +835,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   }
 #pragma unroll
   for (int u = 0; u < MAXT; ++u) {
-    const int q = wave + 4 * u;
+    const int q = t0 + wave + 4 * u;
     if (q >= nm0 + nm1) break;
     const int p = q < nm0 ? 0 : 1;
     const int k = p ? k1 : k0;
@@ -847,6 +850,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       }
     }
   }
+  }  // passes over the output tiles
 }
 
 template <int NT, int ICH, int PREC>
@@ -1137,6 +1141,7 @@ hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock
 
 hipError_t split_factors(sht_plan_s* P, hipStream_t s) {
   if (P->d.fac_hl) return hipSuccess;
+  if (!P->d.fac || !P->d.fac_t) return hipErrorInvalidValue;
   const size_t n = static_cast<size_t>(std::max<long long>(P->n_fac, 4));
   float2* bufs[2] = {nullptr, nullptr};
   for (int b = 0; b < 2; ++b) {

@@ -359,7 +359,6 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
       return SHT_EINVAL;
     if (device < 0) device = q.plan->device;
     if (q.plan->device != device) return SHT_EINVAL;
-    if (precision != SHT_FP64 && q.plan->final_maxk > 192) return SHT_EUNSUPPORTED;
   }
   int prev = -1;
   (void)hipGetDevice(&prev);
@@ -415,6 +414,7 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
       B->groups.push_back(std::move(g));
     }
     if (precision != SHT_FP64 && ensure_split_factors(P, s) != hipSuccess) rc = SHT_EHIP;
+    if (precision == SHT_FP64 && !P->d.fac) rc = SHT_ENOTREADY;  // a split-only plan
   }
   // launch sets: largest workspaces first, first fit under the limit
   if (rc == SHT_OK) {

@@ -56,7 +56,7 @@ class Plan:
     """Butterfly SHT plan for bandlimit l (degrees 0..2l-1) on one GPU."""
 
     def __init__(self, l, eps=1e-13, leaf_width=64, precision="fp64", kind="complex",
-                 host_threads=0, device=None):
+                 host_threads=0, device=None, split_only=False):
         lib = L.load()
         opts = L.PlanOpts()
         lib.sht_default_opts(ctypes.byref(opts))
@@ -64,6 +64,7 @@ class Plan:
         opts.precision = PRECISIONS[precision]
         opts.field_kind = KINDS[kind]
         opts.host_threads = int(host_threads)
+        opts.split_only = 1 if split_only else 0
         if device is None:
             opts.device = -1
         else:
@@ -78,6 +79,16 @@ class Plan:
         self.precision = precision
         self.leaf_width = int(leaf_width)
         self._ws = {}
+        self._prepared = {precision} if split_only else {"fp64", precision}
+
+    def prepare(self, precision, stream=None):
+        """Derive the factor copies a split-FP32 / FP32 transform reads (sht_plan_prepare):
+        plan-owned device memory; waits for the stream.  The transforms call it on the first
+        use of a precision."""
+        if precision not in self._prepared:
+            L.check(L.load().sht_plan_prepare(self._h, PRECISIONS[precision], _stream_handle(stream)),
+                    "sht_plan_prepare")
+            self._prepared.add(precision)
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -209,6 +220,7 @@ class Plan:
             dt = torch.complex128 if self._grid_complex() else torch.float64
             out = torch.empty((F,) + self.grid_shape, dtype=dt, device=coeff.device)
         self._check_tensor(out, self.grid_shape, self._grid_complex(), "grid")
+        self.prepare(precision or self.precision, stream)
         prec = PRECISIONS[precision or self.precision]
         ws = self.workspace(F, precision, coeff.device)
         _used_on(stream, ws, out)
@@ -227,6 +239,7 @@ class Plan:
         if out is None:
             out = torch.empty((F, self.n_coeffs), dtype=torch.complex128, device=grid.device)
         self._check_tensor(out, (self.n_coeffs,), True, "coeff")
+        self.prepare(precision or self.precision, stream)
         prec = PRECISIONS[precision or self.precision]
         ws = self.workspace(F, precision, grid.device)
         _used_on(stream, ws, out)

@@ -53,18 +53,35 @@ def test_roofline_picks_the_largest_launch_and_its_bound():
         "analysis.final/F64/split32": {"ms": 250.0, "launches": 20, "flops": 1.2e11, "bytes": 1.5e10},
         "synth.level2.c0/F64/split32": {"ms": 100.0, "launches": 20, "flops": 4e11, "bytes": 1e10},
     }
-    r = bench.roofline(prof, ms_total=500.0, precision="split32")
+    r = bench.roofline(prof, precision="split32", l=1024, F=64)
     mean_s = 250.0 / 20 / 1e3
-    # 8 flop/byte is below the FP32 ridge (157.3 / 8 = 19.7): bandwidth-bound
-    assert r["kernel"] == "analysis.final/F64/split32" and r["bound"] == "hbm" and r["unit"] == "GB/s"
-    assert abs(r["achieved"] - 1.5e10 / mean_s / 1e9) < 1e-9 and r["peak"] == 8000.0
-    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
-    assert abs(r["share_of_step"] - 0.5) < 1e-12 and r["mean_launch_ms"] == 12.5
-    # the same launch with 40 flop/byte in FP64 is above the FP64 ridge (9.8): matrix-core bound
-    prof["analysis.final/F64/split32"]["flops"] = 6e11
-    r = bench.roofline(prof, ms_total=500.0, precision="fp64")
-    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
-    assert abs(r["achieved"] - 6e11 / mean_s / 1e12) < 1e-9
+    # a Legendre launch at 64 fields is a dense contraction: matrix-core bound, FP64-equivalent
+    # flops against the FP32 MFMA peak the split form runs on, its four products per
+    # FP64-equivalent product given beside it
+    assert r["kernel"] == "analysis.final/F64/split32" and r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert r["peak"] == 157.3 and abs(r["achieved"] - 1.2e11 / mean_s / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12 and r["mean_launch_ms"] == 12.5
+    assert abs(r["executed_frac"] - 4 * r["frac"]) < 1e-12
+    assert r["nonalgorithmic_bytes_per_launch"] == 1.5e10
+    r = bench.roofline(prof, precision="fp64", l=1024, F=64)
+    assert r["bound"] == "mfma" and r["peak"] == 78.6 and abs(r["executed_frac"] - r["frac"]) < 1e-15
+    # an FFT launch that dominates is bound by HBM on the grid bytes it reads or writes once
+    prof["synth.fft/F64/split32"]["ms"] = 400.0
+    r = bench.roofline(prof, precision="split32", l=1024, F=64)
+    gb = 64 * 2048 * 4096 * 16
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert abs(r["achieved"] - gb / 0.02 / 1e9) < 1e-6 and r["nonalgorithmic_bytes_per_launch"] == 8e9 - gb
+
+
+def test_step_roofline_sums_every_launch():
+    prof = {"a": {"ms": 10.0, "launches": 4, "flops": 2e11, "bytes": 1e9},
+            "b": {"ms": 30.0, "launches": 2, "flops": 5e11, "bytes": 3e9}}
+    r = bench.step_roofline(prof, steps=2, ms_step=20.0, precision="split32", l=1024, F=64, fac_entries=1e9)
+    flops = (4 * 2e11 + 2 * 5e11) / 2
+    assert abs(r["flops_per_step"] - flops) < 1 and abs(r["mfma_frac"] - flops / 0.02 / 157.3e12) < 1e-12
+    assert abs(r["executed_mfma_frac"] - 4 * r["mfma_frac"]) < 1e-12
+    algo = 2 * 1e9 * 8 + 2 * 64 * 4 * 1024 ** 2 * 16 + 2 * 64 * 2048 * 4096 * 16
+    assert abs(r["algorithmic_bytes_per_step"] - algo) < 1 and r["layout_bytes_per_step"] == (4e9 + 6e9) / 2
 
 
 def test_stage_totals_merge_size_classes():

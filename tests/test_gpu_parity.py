@@ -173,32 +173,41 @@ def test_split_precision_matches_oracle(l, C, F):
     assert e32.max() < 1e-4
 
 
-def test_full_size_on_sampled_orders():
-    # The benchmark's shape and launch configuration (l = 1024, 64 complex fields, eps 1e-12,
-    # leaf width 64: R = 256 columns, the largest size classes) in split-FP32 and FP64.  The
-    # oracle covers a sample of orders: synthesis of coefficients that vanish outside the
-    # sample (whole grids of two fields), and the sampled orders of the analysis of a seeded
-    # grid (two fields).
-    l, C, F = 1024, 64, 64
+def test_prepare_and_split_only_plans():
+    # A split-FP32 transform needs the split copies of the factors: SHT_ENOTREADY until
+    # sht_plan_prepare derived them (the transforms themselves never allocate).  A split-only
+    # plan frees its FP64 copies: FP64 transforms on it are refused, split ones match the oracle.
+    import ctypes
+
+    from paper_0910_5435_amd import Plan, _lib
+
+    lib = _lib.load()
+    l, C, F = 64, 16, 4
     P = _plan(l, C, eps=1e-12)
-    sample = [0, 1, 300, 1023, 1024, 1800, 2047]
-    ms = np.abs(syn.orders_canonical(l))
-    mask = np.isin(ms, sample)
-    beta = syn.coefficients(l, F, seed=0, power=1.5)
-    beta_s = np.where(mask[None, :], beta, 0.0)
-    f_ref = oracle.synth(beta_s[:2], l, orders=sample)
-    g = syn.grid(l, F, seed=1)
-    a_ref = oracle.analyze_orders(g[:2], l, sample)[:, mask]
-    db, dg = _dev(beta_s), _dev(g)
-    for prec, tol in (("fp64", FP64_TOL), ("split32", SPLIT_TOL)):
-        f = P.synth(db, precision=prec)
-        es = _rel(f[:2].cpu().numpy(), f_ref)
-        del f
-        a = P.analyze(dg, precision=prec)
-        ea = _rel(a[:2].cpu().numpy()[:, mask], a_ref)
-        del a
-        print(f"l={l} F={F} {prec}: synth {es.max():.2e} analysis {ea.max():.2e} (orders {sample})")
-        assert es.max() < tol and ea.max() < tol
+    beta = _dev(syn.coefficients(l, F, seed=0, power=1.5))
+    grid = torch.empty((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
+    ws = P.workspace(F)
+    wp = (ws.data_ptr() + 255) & ~255
+
+    def call(plan, prec):
+        rc = lib.sht_synth_ex(plan.handle, prec, ctypes.c_void_p(beta.data_ptr()),
+                              ctypes.c_void_p(grid.data_ptr()), F, ctypes.c_void_p(wp), ws.numel() - 256, None)
+        torch.cuda.synchronize()
+        return rc
+
+    assert call(P, _lib.SHT_SPLIT32) == _lib.SHT_ENOTREADY
+    assert lib.sht_plan_prepare(P.handle, _lib.SHT_SPLIT32, None) == _lib.SHT_OK
+    assert call(P, _lib.SHT_SPLIT32) == _lib.SHT_OK
+    ref = oracle.synth(beta.cpu().numpy(), l)
+    assert _rel(grid.cpu().numpy(), ref).max() < SPLIT_TOL
+    S = Plan(l, eps=1e-12, leaf_width=C, precision="split32", split_only=True)
+    assert S.stats()["device_bytes"] < P.stats()["device_bytes"]
+    assert call(S, _lib.SHT_FP64) == _lib.SHT_ENOTREADY
+    assert lib.sht_plan_prepare(S.handle, _lib.SHT_FP64, None) == _lib.SHT_ENOTREADY
+    assert _rel(S.synth(beta, precision="split32").cpu().numpy(), ref).max() < SPLIT_TOL
+    with pytest.raises(_lib.ShtError) as ei:
+        Plan(l, eps=1e-12, leaf_width=C, precision="fp64", split_only=True)
+    assert ei.value.status == _lib.SHT_EINVAL
 
 
 def test_split_precision_real_fields_and_adjoint():
