@@ -13,6 +13,8 @@ SHT_EUNSUPPORTED = -4
 SHT_EINTERNAL = -5
 SHT_ENOTREADY = -6
 
+NOALLOC_SCRATCH_BYTES = 256 << 20  # SHT_NOALLOC_SCRATCH_BYTES of include/sht.h
+
 SHT_FP64 = 0
 SHT_SPLIT32 = 1
 SHT_FP32 = 2
@@ -114,6 +116,7 @@ SIGNATURES = {
     "sht_analyze": (_I, [_P, _P, _P, _I, _P, _S, _P]),
     "sht_synth_adjoint": (_I, [_P, _P, _P, _I, _P, _S, _P]),
     "sht_synth_ex": (_I, [_P, _I, _P, _P, _I, _P, _S, _P]),
+    "sht_synth_noalloc": (_I, [_P, _P, _P, _I, _P]),
     "sht_analyze_ex": (_I, [_P, _I, _P, _P, _I, _P, _S, _P]),
     "sht_synth_adjoint_ex": (_I, [_P, _I, _P, _P, _I, _P, _S, _P]),
     "sht_plan_stats": (_I, [_P, ctypes.POINTER(Stats)]),

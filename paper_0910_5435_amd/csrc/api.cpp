@@ -165,9 +165,10 @@ Work layout_work(const sht_plan_s* P, int F, int R) {
   return {0.0, 16.0 * ncoef * F + 8.0 * P->rows_in * R};
 }
 
-// Runs one launch; with profiling on, brackets it with events on the stream.
-template <typename Fn>
-int stage(sht_plan_s* P, hipStream_t s, const std::string& name, Work w, Fn&& launch) {
+// Runs one launch; with profiling on (prof), brackets it with events on the stream.  The
+// stage name and work are evaluated only then, so an unprofiled call builds no strings.
+template <typename Name, typename Fn>
+int stage(sht_plan_s* P, hipStream_t s, bool prof, Name&& name, Fn&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   int rec = -1;
   auto fail = [&]() {
@@ -175,22 +176,25 @@ int stage(sht_plan_s* P, hipStream_t s, const std::string& name, Work w, Fn&& la
     if (b) (void)hipEventDestroy(b);
     return SHT_EHIP;
   };
-  if (P->prof.on) {
-    rec = P->prof.find_or_add(name, w.flops, w.bytes);
+  if (prof) {
+    const std::pair<std::string, Work> nw = name();
+    rec = P->prof.find_or_add(nw.first, nw.second.flops, nw.second.bytes);
     if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) return fail();
   }
   if (launch() != hipSuccess) return fail();
-  if (P->prof.on) {
+  if (prof) {
     if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) return fail();
     P->prof.pending.push_back({rec, a, b});
   }
   return SHT_OK;
 }
 
-#define STAGE(name, work, call)                          \
-  do {                                                   \
-    int _rc = stage(P, s, (name), (work), [&]() { return (call); }); \
-    if (_rc != SHT_OK) return _rc;                       \
+// `prof` (bool) must be in scope: profiling wanted for this call.
+#define STAGE(name, work, call)                                                          \
+  do {                                                                                   \
+    int _rc = stage(P, s, prof, [&]() { return std::pair<std::string, Work>((name), (work)); }, \
+                    [&]() { return (call); });                                           \
+    if (_rc != SHT_OK) return _rc;                                                       \
   } while (0)
 
 std::string fsuffix(int F, int precision) {
@@ -198,8 +202,14 @@ std::string fsuffix(int F, int precision) {
   return "/F" + std::to_string(F) + tag;
 }
 
+}  // namespace
+
+namespace sht {
+
+// Synthesis into the caller's workspace; allow_prof = false runs without the per-stage events
+// even when the plan's profiler is on (no event objects, no strings: nothing is allocated).
 int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, int F, void* ws,
-              size_t wsb, void* stream) {
+              size_t wsb, void* stream, bool allow_prof) {
   int rc = check_call(P, precision, coeff, grid, F, ws, wsb);
   if (rc) return rc;
   DeviceScope ds(P->device);
@@ -207,7 +217,8 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
-  const std::string fs = fsuffix(F, precision);
+  const bool prof = allow_prof && P->prof.on;
+  const std::string fs = prof ? fsuffix(F, precision) : std::string();
   // matrix-core path: one stage per size-class launch ("synth.level2.c1/F64/fp64"), so that every
   // timed stage is exactly one kernel dispatch; the leaf kernels gather straight from the
   // coefficient layout
@@ -250,6 +261,12 @@ int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, i
   return SHT_OK;
 }
 
+size_t synth_workspace_bytes(const sht_plan_s* P, int F) { return ws_bytes(P, F); }
+
+}  // namespace sht
+
+namespace {
+
 int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coeff, int F, void* ws,
                    size_t wsb, void* stream, bool adjoint) {
   int rc = check_call(P, precision, grid, coeff, F, ws, wsb);
@@ -260,8 +277,9 @@ int run_transposed(sht_plan_s* P, int precision, const double* grid, double* coe
   const int R = field_width(P, F);
   Workspace w = carve(P, F, ws);
   const double scale = adjoint ? 1.0 : 1.0 / (4.0 * P->l);
+  const bool prof = P->prof.on;
   const std::string pre = adjoint ? "adjoint." : "analysis.";
-  const std::string fs = fsuffix(F, precision);
+  const std::string fs = prof ? fsuffix(F, precision) : std::string();
   STAGE(pre + "fft" + fs, fft_work(P, F, R),
         launch_fft_analyze(P, grid, w.y, F, R, scale, adjoint ? 2.0 : 1.0, s));
   STAGE(pre + "final" + fs, final_work(P, R),
@@ -386,7 +404,7 @@ size_t sht_workspace_bytes(sht_plan_t plan, int nfields, int precision) {
 
 int sht_synth(sht_plan_t plan, const double* coeff, double* grid, int F, void* ws, size_t wsb,
               void* stream) {
-  return plan ? run_synth(plan, plan->precision, coeff, grid, F, ws, wsb, stream) : SHT_EINVAL;
+  return plan ? run_synth(plan, plan->precision, coeff, grid, F, ws, wsb, stream, true) : SHT_EINVAL;
 }
 int sht_analyze(sht_plan_t plan, const double* grid, double* coeff, int F, void* ws, size_t wsb,
                 void* stream) {
@@ -400,7 +418,7 @@ int sht_synth_adjoint(sht_plan_t plan, const double* grid_cot, double* coeff_cot
 }
 int sht_synth_ex(sht_plan_t plan, int prec, const double* coeff, double* grid, int F, void* ws,
                  size_t wsb, void* stream) {
-  return run_synth(plan, prec, coeff, grid, F, ws, wsb, stream);
+  return run_synth(plan, prec, coeff, grid, F, ws, wsb, stream, true);
 }
 int sht_analyze_ex(sht_plan_t plan, int prec, const double* grid, double* coeff, int F, void* ws,
                    size_t wsb, void* stream) {

@@ -233,6 +233,10 @@ hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, 
 hipError_t launch_fft_analyze(const sht_plan_s* P, const double* grid, double* y, int F, int R,
                               double scale, double real_pos, hipStream_t s,
                               double* const* fptr = nullptr);
+// Synthesis (api.cpp) into the caller's workspace; allow_prof = false: no per-stage events.
+int run_synth(sht_plan_s* P, int precision, const double* coeff, double* grid, int F, void* ws,
+              size_t wsb, void* stream, bool allow_prof);
+size_t synth_workspace_bytes(const sht_plan_s* P, int F);
 hipError_t fft_prepare(int l);  // kernel attributes for 4l-point rows (before graph capture)
 hipError_t split_factors(sht_plan_s* P, hipStream_t s);
 // split_factors under the plan's lock: calls from several host threads derive the copies once.
