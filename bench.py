@@ -30,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "SHT synth+analysis pairs/s at l=1024, 64 fields: split-FP32 vs FP64, 1e-9 err"
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "int8": 5.0e15, "hbm": 8.0e12}
 
 
 def parse():
@@ -42,7 +42,7 @@ def parse():
                     help="steps (each F single-field pairs) for the per-field FP64 variant")
     ap.add_argument("--l", type=int, default=1024)
     ap.add_argument("--fields", type=int, default=64)
-    ap.add_argument("--precision", default="split32", choices=["fp64", "split32", "fp32"])
+    ap.add_argument("--precision", default="split32", choices=["fp64", "split32", "fp32", "int8"])
     ap.add_argument("--no-variants", action="store_true", help="time only --precision")
     ap.add_argument("--leaf-width", type=int, default=64)
     ap.add_argument("--eps", type=float, default=1e-12)
@@ -103,7 +103,7 @@ def oracle_check(plan, args, beta_np):
     g_in = torch.zeros((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda")
     g_in[fo] = torch.from_numpy(f_ref).to("cuda")
     errs = {}
-    for prec in dict.fromkeys([args.precision, "fp64"] + ([] if args.no_variants else ["split32"])):
+    for prec in dict.fromkeys([args.precision, "fp64"] + ([] if args.no_variants else ["split32", "int8"])):
         f_gpu = plan.synth(dev_b, precision=prec)[fo].cpu().numpy()
         a_gpu = plan.analyze(g_in, precision=prec)[fo].cpu().numpy()
         errs[prec] = {
@@ -301,7 +301,12 @@ def measured_traffic(launch):
     return ent["bytes"]
 
 
-PRODUCTS = {"fp64": 1, "split32": 4, "fp32": 1}  # MFMA products per FP64-equivalent product
+PRODUCTS = {"fp64": 1, "split32": 4, "fp32": 1, "int8": 15}  # MFMA products per FP64-equivalent product
+
+
+def unit_peak(precision):
+    """Dense peak of the matrix-core unit a form runs on (FP64, FP32 or int8 MFMA)."""
+    return {"fp64": PEAK["fp64"], "split32": PEAK["fp32"], "fp32": PEAK["fp32"], "int8": PEAK["int8"]}[precision]
 
 
 def grid_bytes(l, F):
@@ -320,7 +325,7 @@ def roofline(prof, precision, l, F):
     it also moves is not algorithmic and is reported separately."""
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     mean_s = rec["ms"] / rec["launches"] / 1e3
-    peak_f = PEAK["fp64"] if precision == "fp64" else PEAK["fp32"]
+    peak_f = unit_peak(precision)
     if ".fft/" not in name:
         roof = {"bound": "mfma", "achieved": rec["flops"] / mean_s / 1e12, "peak": peak_f / 1e12,
                 "unit": "TFLOP/s", "frac": rec["flops"] / mean_s / peak_f,
@@ -345,7 +350,7 @@ def step_roofline(prof, steps, ms_step, precision, l, F, fac_entries):
     algorithmic HBM bytes of the method (factors read once per direction, coefficients and
     grid each read or written once per direction)."""
     flops = sum(v["flops"] * v["launches"] for v in prof.values()) / steps
-    peak_f = PEAK["fp64"] if precision == "fp64" else PEAK["fp32"]
+    peak_f = unit_peak(precision)
     coef_bytes = float(F) * 4 * l * l * 16
     fac_bytes = 2.0 * fac_entries * 8
     algo_bytes = fac_bytes + 2 * coef_bytes + 2 * grid_bytes(l, F)
@@ -482,7 +487,8 @@ def main():
     print(f"# plan l={l} eps={args.eps} C={args.leaf_width}: {t_plan:.1f} s, k_max={st['k_max']} "
           f"k_avg={st['k_avg']:.1f} factors={st['factor_entries']:.3e} (columns {st['t_columns_s']:.1f} s, "
           f"IDs {st['t_compress_s']:.1f} s)", file=sys.stderr, flush=True)
-    precs = [args.precision] if args.no_variants else list(dict.fromkeys([args.precision, "fp64", "split32", "fp32"]))
+    precs = [args.precision] if args.no_variants else list(
+        dict.fromkeys([args.precision, "fp64", "split32", "fp32", "int8"]))
     for prec in precs:
         plan.prepare(prec)
 
@@ -568,7 +574,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "split32": "f32-split (FP32 MFMA products, f64 accumulation)",
-                  "fp32": "f32"}[args.precision],
+                  "fp32": "f32", "int8": "i8-slices (int8 MFMA digit products, f64 combination)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"SHT synthesis+analysis, l={l} (degrees 0..{2 * l - 1}), {F} complex "
                                f"fields, grid {2 * l}x{4 * l}, coefficients CN(0,1)/(1+k)^{args.power}",
@@ -596,7 +602,7 @@ def main():
         # gate: every checked field in both directions within GATE of the oracle, and every
         # field of the batch within GATE once its distance to the FP64 butterfly is added to the
         # FP64 butterfly's own largest distance to the oracle
-        tol = {"fp64": 1e-11, "split32": GATE, "fp32": 1e-4}
+        tol = {"fp64": 1e-11, "split32": GATE, "int8": GATE, "fp32": 1e-4}
         e64 = max(max(chk["rel_l2"]["fp64"]["synth"]), max(chk["rel_l2"]["fp64"]["analysis"]))
         bound = {p: max(v["synth_max"], v["analysis_max"]) + e64 for p, v in err64.items()}
         checked = {p: max(max(v["synth"]), max(v["analysis"])) for p, v in chk["rel_l2"].items()}

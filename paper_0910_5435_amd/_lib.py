@@ -18,6 +18,7 @@ NOALLOC_SCRATCH_BYTES = 256 << 20  # SHT_NOALLOC_SCRATCH_BYTES of include/sht.h
 SHT_FP64 = 0
 SHT_SPLIT32 = 1
 SHT_FP32 = 2
+SHT_INT8 = 3
 
 SHT_COMPLEX = 0
 SHT_REAL = 1

@@ -120,11 +120,12 @@ class DeviceScope {
 int check_call(const sht_plan_s* P, int precision, const void* a, const void* b, int F, void* ws,
                size_t wsb) {
   if (!P || !a || !b || F < 1 || !ws) return SHT_EINVAL;
-  if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
-  // the split and FP32 variants run on the matrix-core kernels only (R a multiple of 16), on
-  // factor copies that sht_plan_prepare (or a plan built for that precision) derived
+  if (precision < SHT_FP64 || precision > SHT_INT8) return SHT_EINVAL;
+  // the split, FP32 and int8 forms run on the matrix-core kernels only (R a multiple of 16),
+  // on factor copies that sht_plan_prepare (or a plan built for that precision) derived
   if (precision != SHT_FP64 && !mfma_ok(field_width(P, F))) return SHT_EUNSUPPORTED;
-  if (precision != SHT_FP64 && !P->d.fac_hl) return SHT_ENOTREADY;
+  if ((precision == SHT_SPLIT32 || precision == SHT_FP32) && !P->d.fac_hl) return SHT_ENOTREADY;
+  if (precision == SHT_INT8 && !P->d.dig) return SHT_ENOTREADY;
   if (precision == SHT_FP64 && !P->d.fac) return SHT_ENOTREADY;  // a split-only plan
   if (reinterpret_cast<uintptr_t>(a) % 16 || reinterpret_cast<uintptr_t>(b) % 16) return SHT_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) % 256) return SHT_EINVAL;
@@ -198,7 +199,10 @@ int stage(sht_plan_s* P, hipStream_t s, bool prof, Name&& name, Fn&& launch) {
   } while (0)
 
 std::string fsuffix(int F, int precision) {
-  const char* tag = precision == SHT_SPLIT32 ? "/split32" : precision == SHT_FP32 ? "/fp32" : "/fp64";
+  const char* tag = precision == SHT_SPLIT32 ? "/split32"
+                    : precision == SHT_FP32  ? "/fp32"
+                    : precision == SHT_INT8  ? "/int8"
+                                             : "/fp64";
   return "/F" + std::to_string(F) + tag;
 }
 
@@ -336,7 +340,7 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   if (o.leaf_width == 0) o.leaf_width = 64;
   if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 1 || o.leaf_width > 4096)
     return SHT_EINVAL;
-  if (o.precision < SHT_FP64 || o.precision > SHT_FP32) return SHT_EINVAL;
+  if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
   if (o.field_kind != SHT_COMPLEX && o.field_kind != SHT_REAL) return SHT_EINVAL;
   if (o.split_only && o.precision == SHT_FP64) return SHT_EINVAL;
   if (!pow2(l) || l > 2048) return SHT_EUNSUPPORTED;
@@ -360,9 +364,12 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   } catch (...) {
     rc = SHT_EINTERNAL;
   }
-  // a plan built for a split or FP32 default derives those factor copies now, so that its
-  // transforms never allocate or wait
-  if (rc == SHT_OK && P->precision != SHT_FP64 && split_factors(P, nullptr) != hipSuccess) rc = SHT_EHIP;
+  // a plan built for a split, FP32 or int8 default derives those factor copies now, so that
+  // its transforms never allocate or wait
+  if (rc == SHT_OK && (P->precision == SHT_SPLIT32 || P->precision == SHT_FP32) &&
+      split_factors(P, nullptr) != hipSuccess)
+    rc = SHT_EHIP;
+  if (rc == SHT_OK && P->precision == SHT_INT8 && i8_prepare(P, nullptr) != hipSuccess) rc = SHT_EHIP;
   if (rc == SHT_OK && o.split_only) {
     (void)hipFree(P->d.fac);
     (void)hipFree(P->d.fac_t);
@@ -380,11 +387,18 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
 
 int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
   if (!plan) return SHT_EINVAL;
-  if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
+  if (precision < SHT_FP64 || precision > SHT_INT8) return SHT_EINVAL;
   if (precision == SHT_FP64) return plan->d.fac ? SHT_OK : SHT_ENOTREADY;
   DeviceScope ds(plan->device);
   if (!ds.ok()) return SHT_EHIP;
-  const hipError_t e = ensure_split_factors(plan, static_cast<hipStream_t>(stream));
+  if (!plan->d.fac && ((precision == SHT_INT8 && !plan->d.dig) || (precision != SHT_INT8 && !plan->d.fac_hl)))
+    return SHT_ENOTREADY;  // a split-only plan no longer holds the FP64 factors they come from
+  hipError_t e;
+  {
+    std::lock_guard<std::mutex> lock(plan->split_mu);
+    e = precision == SHT_INT8 ? i8_prepare(plan, static_cast<hipStream_t>(stream))
+                              : split_factors(plan, static_cast<hipStream_t>(stream));
+  }
   if (e == hipErrorOutOfMemory) return SHT_ENOMEM;
   return e == hipSuccess ? SHT_OK : SHT_EHIP;
 }
@@ -398,7 +412,7 @@ void sht_destroy(sht_plan_t plan) {
 }
 
 size_t sht_workspace_bytes(sht_plan_t plan, int nfields, int precision) {
-  if (!plan || nfields < 1 || precision < SHT_FP64 || precision > SHT_FP32) return 0;
+  if (!plan || nfields < 1 || precision < SHT_FP64 || precision > SHT_INT8) return 0;
   return ws_bytes(plan, nfields);
 }
 

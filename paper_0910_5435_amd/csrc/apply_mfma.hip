@@ -1174,6 +1174,7 @@ bool mfma_ok(int R) { return R % 16 == 0; }
 
 hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, const double* in,
                              double* out, int R, int precision, hipStream_t s, double* coeff, int only) {
+  if (precision == SHT_INT8) return launch_level_i8(P, step, transpose, in, out, R, s, coeff, only);
   CoefIO io{coeff, nullptr,
             P->kind == SHT_COMPLEX ? 4LL * P->l * P->l : 2LL * P->l * P->l + P->l, P->l, P->kind};
   for (size_t c = 0; c < P->step_classes[step].size(); ++c) {
@@ -1195,6 +1196,7 @@ hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* 
                              double* v0w, double* v1w, double* y, const double* yin, int R,
                              int precision, bool adjoint, hipStream_t s, int only) {
   if (P->n_final == 0) return hipSuccess;
+  if (precision == SHT_INT8) return launch_final_i8(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s, only);
   if (precision == SHT_SPLIT32)
     return final_launch<PSPLIT>(P, transpose, v0, v1, v0w, v1w, y, yin, R, adjoint, s, only);
   if (precision == SHT_FP32)

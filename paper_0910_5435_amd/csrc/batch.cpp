@@ -349,6 +349,7 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
   *out = nullptr;
   if (!reqs || nreq < 1) return SHT_EINVAL;
   if (op != SHT_BATCH_SYNTH && op != SHT_BATCH_ANALYZE && op != SHT_BATCH_ADJOINT) return SHT_EINVAL;
+  if (precision == SHT_INT8) return SHT_EUNSUPPORTED;  // the persistent kernel has no int8 form
   if (precision != SHT_FP64 && precision != SHT_SPLIT32 && precision != SHT_FP32) return SHT_EINVAL;
   const size_t limit = workspace_limit ? workspace_limit : kDefaultWsLimit;
   int device = -1;

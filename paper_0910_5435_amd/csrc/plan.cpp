@@ -353,14 +353,33 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   P->step_fac.assign(Lmax + 1, 0.0);
   P->step_rows_in.assign(Lmax + 1, 0.0);
   P->step_rows_out.assign(Lmax + 1, 0.0);
+  // Places of every stored matrix in the int8-slice pools (both orientations), filled by
+  // sht_plan_prepare; only the offsets are laid out here.
+  long long dig_off = 0, dex_off = 0;
+  std::vector<I8Block> i8b;
+  auto i8_place = [&](int64_t fac_off, int rows, int cols, I8Off& o) {
+    o = I8Off{};
+    if (rows <= 0 || cols <= 0) return;
+    o.dig[0] = dig_off;
+    dig_off += i8_tile_bytes(rows, cols);
+    o.dig[1] = dig_off;
+    dig_off += i8_tile_bytes(cols, rows);
+    o.ex[0] = dex_off;
+    dex_off += i8_exp_count(rows);
+    o.ex[1] = dex_off;
+    dex_off += i8_exp_count(cols);
+    i8b.push_back({fac_off, rows, cols, o});
+  };
   // map (may be null): renumbering of the block's input indices (folded leaves, below)
-  auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off, const std::vector<int>* map) {
+  auto push_block = [&](const BfBlock& B, int32_t& idx_off, int64_t& fac_off, I8Off& i8o,
+                        const std::vector<int>* map) {
     idx_off = static_cast<int32_t>(idx.size());
     for (int v : B.skel) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
     for (int v : B.red) idx.push_back(static_cast<uint16_t>(map ? (*map)[v] : v));
     fac_off = static_cast<int64_t>(fac.size());
     fac.append(B.T.data(), B.T.size());
     if (!B.T.empty()) fblocks.push_back({fac_off, B.k, B.K - B.k});
+    i8_place(fac_off, B.T.empty() ? 0 : B.k, B.K - B.k, i8o);
   };
   // Tasks of a step are independent; they are grouped into size classes (by input length
   // K) so that each class launches with an LDS allocation fitting its own blocks, largest
@@ -451,11 +470,11 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
       Proto& pr = protos[i];
       LevelTask tk = pr.tk;
       const std::vector<int>* map = pr.map.empty() ? nullptr : &pr.map;
-      push_block(*pr.b[0], tk.idx[0], tk.fac[0], map);
+      push_block(*pr.b[0], tk.idx[0], tk.fac[0], tk.i8[0], map);
       int kmx = pr.b[0]->k;
       double nf = static_cast<double>(pr.b[0]->T.size());
       if (pr.b[1]) {
-        push_block(*pr.b[1], tk.idx[1], tk.fac[1], map);
+        push_block(*pr.b[1], tk.idx[1], tk.fac[1], tk.i8[1], map);
         kmx = std::max(kmx, pr.b[1]->k);
         nf += static_cast<double>(pr.b[1]->T.size());
       }
@@ -466,6 +485,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
       cls.back().cnt += 1;
       cls.back().maxK = std::max(cls.back().maxK, tk.K);
       cls.back().maxk = std::max(cls.back().maxk, kmx);
+      cls.back().maxnr = std::max(cls.back().maxnr, tk.K - std::min(tk.k[0], tk.k[1] < 0 ? tk.k[0] : tk.k[1]));
       cls.back().fac += nf;
       cls.back().rows_in += tk.K;
       cls.back().rows_out += tk.k[0] + (tk.k[1] > 0 ? tk.k[1] : 0);
@@ -516,6 +536,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
       ft.fac[p] = static_cast<int64_t>(fac.size());
       fac.append(f.S.data(), f.S.size());
       if (!f.S.empty()) fblocks.push_back({ft.fac[p], f.h, f.k});
+      i8_place(ft.fac[p], f.S.empty() ? 0 : f.h, f.k, ft.i8[p]);
     }
     const int kmx = std::max(ft.k[0], ft.k[1]);
     const int cl = fclass(kmx);
@@ -524,6 +545,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     P->final_classes.back().cnt += 1;
     P->final_classes.back().maxK = std::max(P->final_classes.back().maxK, ft.h);
     P->final_classes.back().maxk = std::max(P->final_classes.back().maxk, kmx);
+    P->final_classes.back().maxnr = std::max(P->final_classes.back().maxnr, kmx);
     P->final_classes.back().fac += static_cast<double>(ft.h) * (ft.k[0] + ft.k[1]);
     P->final_classes.back().rows_in += ft.k[0] + ft.k[1];
     P->final_classes.back().rows_out += 2.0 * ft.h;
@@ -536,6 +558,8 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   }
   P->n_final = static_cast<long long>(finals.size());
   P->n_fac = static_cast<long long>(fac.size());
+  P->n_dig = dig_off;
+  P->n_dex = dex_off;
   P->n_idx = static_cast<long long>(idx.size());
   {
     const int rc = fac.close();
@@ -588,6 +612,9 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   P->d.blocks = dblocks;  // kept: the split copies are derived from it on first use
   P->n_blocks = static_cast<long long>(fblocks.size());
+  if (e == hipSuccess && i8b.size() != fblocks.size()) return SHT_EINTERNAL;
+  if (e == hipSuccess)
+    e = up(reinterpret_cast<void**>(&P->d.i8blocks), i8b.data(), i8b.size() * sizeof(I8Block));
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   P->stats.device_bytes =
       static_cast<long long>(2 * n_fac_total * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
@@ -597,9 +624,9 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
 }
 
 void free_plan_device(sht_plan_s* P) {
-  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hl, P->d.fac_t_hl,
-                  P->d.blocks, P->d.idx,    P->d.tasks,  P->d.finals,
-                  P->d.pairs,  P->d.invD,     P->d.D,      P->d.twiddle};
+  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hl, P->d.fac_t_hl, P->d.dig,
+                  P->d.dex,    P->d.i8blocks, P->d.blocks, P->d.idx,      P->d.tasks,
+                  P->d.finals, P->d.pairs,    P->d.invD,   P->d.D,        P->d.twiddle};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   P->d = DeviceFactors{};

@@ -12,6 +12,15 @@
 
 namespace sht {
 
+// Int8-slice form: where one stored matrix M (rows x cols) lives in the int8 pools, in the
+// orientation each direction contracts with: 0 = M itself (synthesis), 1 = M^T (transposed
+// apply).  Both are tile-packed signed 8-bit digits (16 rows x 64 contraction indices x the
+// digits per 5 KiB block) with one int16 exponent per (padded) row.
+struct I8Off {
+  int64_t dig[2];  // byte offsets of the digit tiles of M and of M^T
+  int64_t ex[2];   // offsets (int16 units) of the row exponents of M and of M^T
+};
+
 // One butterfly interpolation task: a leaf ID (one output) or a merged pair of
 // row-split IDs that share their input (two outputs, top and bottom; Section
 // 2.2 equations (top), (bottom)).  Rows are indices of R-wide rows in the
@@ -26,6 +35,7 @@ struct LevelTask {
   int32_t mp;         // pair index 2m + p if the input rows are coefficients (leaf tasks, and
                       // level-1 tasks over folded identity leaves), else -1
   int64_t fac[2];     // offset of T (k x (K-k), column-major) in the factor pool
+  I8Off i8[2];        // the same T in the int8-slice pools
 };
 
 // Position of Re/Im part `c` of beta_k^{+-m} (s = 0: +m, s = 1: -m) of field f in the
@@ -55,6 +65,7 @@ struct FinalTask {
   int32_t vbuf;       // which V buffer holds them (L % 2)
   int32_t pad;
   int64_t fac[2];     // S (h x k, column-major) offsets
+  I8Off i8[2];        // the same S in the int8-slice pools
 };
 
 // Layout descriptor of one (m, p) pair in the internal coefficient buffer.
@@ -69,12 +80,32 @@ struct FactorBlock {
   int32_t rows, cols;
 };
 
+// A stored matrix and its place in the int8-slice pools (input of the digit preparation).
+struct I8Block {
+  int64_t off;        // FP64 offset in the factor pool (column-major rows x cols)
+  int32_t rows, cols;
+  I8Off o;
+};
+
+// Int8-slice digits per entry and the highest product level kept (digit pairs s + u <= kI8Top
+// of the kI8Dig x kI8Dig products; s = 0 is the most significant digit).
+constexpr int kI8Dig = 6;
+constexpr int kI8Top = 5;
+// Bytes of the digit tiles of an A operand with `rows` rows and `kd` contraction indices.
+inline long long i8_tile_bytes(long long rows, long long kd) {
+  return ((rows + 15) / 16) * ((kd + 63) / 64) * kI8Dig * 1024LL;
+}
+inline long long i8_exp_count(long long rows) { return ((rows + 15) / 16) * 16; }
+
 struct DeviceFactors {
   double* fac = nullptr;       // T and S entries (FP64), column-major, read by synthesis
   double* fac_t = nullptr;     // the same matrices transposed (same offsets), read by analysis
   float2* fac_hl = nullptr;    // split copies (first use of a split/FP32 transform): per entry
                                // the leading slice on its row's grid and the FP32 remainder
   float2* fac_t_hl = nullptr;  // the same for the transposed copies
+  int8_t* dig = nullptr;       // int8-slice digit tiles, both orientations (sht_plan_prepare)
+  int16_t* dex = nullptr;      // their row exponents
+  I8Block* i8blocks = nullptr; // every stored matrix with its int8 offsets (for the preparation)
   FactorBlock* blocks = nullptr;  // every stored matrix (offset, rows, cols)
   uint16_t* idx = nullptr;     // skel/red index lists
   LevelTask* tasks = nullptr;  // all level tasks, step by step
@@ -112,6 +143,8 @@ struct LaunchClass {
   long long off, cnt;  // task range relative to the step's first task
   int maxK, maxk;      // largest input length and output rank in the range
   int cls;
+  int maxnr = 0;       // largest contraction length of the synthesis orientation (K - k;
+                       // finals: largest rank) in the range
   // algorithmic work per R column: factor entries, vector rows read and written
   double fac = 0.0, rows_in = 0.0, rows_out = 0.0;
 };
@@ -194,6 +227,7 @@ struct sht_plan_s {
   std::vector<int> in_base, v_base, v_rows;
   long long rows_in = 0, rows_v = 0, rows_y = 0;
   long long n_fac = 0, n_fac_split = 0, n_idx = 0, n_blocks = 0;
+  long long n_dig = 0, n_dex = 0;       // int8-slice pool sizes (bytes, int16 exponents)
   std::vector<long long> step_off, step_cnt;  // level tasks per step (t = 0..Lmax)
   std::vector<int> step_maxK, step_maxk;      // largest input / output length per step
   std::vector<std::vector<sht::LaunchClass>> step_classes;
@@ -250,6 +284,13 @@ hipError_t launch_level_mfma(const sht_plan_s* P, int step, bool transpose, cons
 hipError_t launch_final_mfma(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                              double* v0w, double* v1w, double* y, const double* yin, int R,
                              int precision, bool adjoint, hipStream_t s, int cls = -1);
+// Int8-slice form (apply_i8.hip): digit pools of the plan (i8_prepare, synchronises s) and
+// the level / final launches of one step (cls >= 0: that size class only).
+hipError_t i8_prepare(sht_plan_s* P, hipStream_t s);
+hipError_t launch_level_i8(const sht_plan_s* P, int step, bool transpose, const double* in, double* out, int R,
+                           hipStream_t s, double* coeff, int cls);
+hipError_t launch_final_i8(const sht_plan_s* P, bool transpose, const double* v0, const double* v1, double* v0w,
+                           double* v1w, double* y, const double* yin, int R, bool adjoint, hipStream_t s, int cls);
 hipError_t transpose_factors(const double* fac, double* fac_t, const FactorBlock* blocks,
                              long long nblocks, hipStream_t s);
 // Persistent batched kernel (column tile nt = 16 or 32): sets the LDS attribute and returns

@@ -10,7 +10,7 @@ import numpy as np
 
 from . import _lib as L
 
-PRECISIONS = {"fp64": L.SHT_FP64, "split32": L.SHT_SPLIT32, "fp32": L.SHT_FP32}
+PRECISIONS = {"fp64": L.SHT_FP64, "split32": L.SHT_SPLIT32, "fp32": L.SHT_FP32, "int8": L.SHT_INT8}
 KINDS = {"complex": L.SHT_COMPLEX, "real": L.SHT_REAL}
 
 

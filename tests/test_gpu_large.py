@@ -1,6 +1,6 @@
 """GPU parity at the largest sizes: the benchmark's batch on every order, bandlimit 2048, and the
 mixed-request workload at its own bandlimits.  Everything runs through the C ABI and is compared
-with the CPU oracle (relative l2 per field; FP64 gate 1e-11, split-FP32 gate 1e-9).
+with the CPU oracle (relative l2 per field; FP64 gate 1e-11, split-FP32 and int8-slice gate 1e-9).
 
 The tests of this module share their plans (an l = 2048 plan takes tens of seconds to build and
 tens of GB of device memory): plans of one form (FP64 only, or split-FP32 only) are kept until a
@@ -88,6 +88,7 @@ def test_l1024_64_fields_every_order():
 
     l, C, F = 1024, 64, 64
     P = Plan(l, eps=1e-12, leaf_width=C, precision="split32")  # keeps its FP64 copies too
+    P.prepare("int8")
     beta = syn.coefficients(l, F, seed=0, power=1.5)
     g4 = syn.grid(l, len(CHECK_FIELDS), seed=1)
     f_ref = oracle.synth(beta[CHECK_FIELDS], l, fast=True)
@@ -98,7 +99,7 @@ def test_l1024_64_fields_every_order():
     gen = torch.Generator(device="cuda").manual_seed(1)
     dg = torch.randn((F, 2 * l, 4 * l), dtype=torch.complex128, device="cuda", generator=gen)
     dg[CHECK_FIELDS] = _dev(g4)
-    for prec, tol in (("fp64", FP64_TOL), ("split32", SPLIT_TOL)):
+    for prec, tol in (("fp64", FP64_TOL), ("split32", SPLIT_TOL), ("int8", SPLIT_TOL)):
         es = _rel(P.synth(db, precision=prec)[CHECK_FIELDS].cpu().numpy(), f_ref)
         ea = _rel(P.analyze(dg, precision=prec)[CHECK_FIELDS].cpu().numpy(), a_ref)
         print(f"l=1024 F=64 {prec}, every order, fields {CHECK_FIELDS}: synthesis {es.max():.2e}, "
@@ -135,11 +136,14 @@ def test_l2048_column_kernel_matches_oracle():
     print(f"l=2048 columns: max abs diff vs oracle {worst:.3e}", flush=True)
 
 
-def _top_parity(form, tol):
+def _top_parity(form, tol, precision=None):
     # l = 2048, four complex fields (R = 16: the matrix-core kernels), sampled orders:
     # synthesis of coefficients that vanish outside the sample (whole grids compared) and the
     # sampled orders of the analysis of a seeded grid.
     P = _plan(L_TOP, form, C=64)
+    if precision:
+        P.prepare(precision)
+    form = precision or form
     F = 4
     beta_s, mask = _only_orders(syn.coefficients(L_TOP, F, seed=0, power=1.5), L_TOP, TOP_ORDERS)
     f_ref = oracle.synth(beta_s, L_TOP, orders=TOP_ORDERS, fast=True)
@@ -156,6 +160,7 @@ def _top_parity(form, tol):
 @pytest.mark.timeout(600)
 def test_l2048_fp64_matches_oracle():
     _top_parity("fp64", FP64_TOL)
+
 
 
 # ---------------------------------------------------------------- mixed-request workload
@@ -232,6 +237,12 @@ def _c4(form, tol):
 @pytest.mark.timeout(900)
 def test_c4_full_bandlimits_fp64():
     _c4("fp64", FP64_TOL)
+
+
+@pytest.mark.timeout(600)
+def test_l2048_int8_matches_oracle():
+    # the int8-slice digits derived on the FP64 plan (after the mixed workload freed its data)
+    _top_parity("fp64", SPLIT_TOL, precision="int8")
 
 
 @pytest.mark.timeout(600)

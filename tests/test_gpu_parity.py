@@ -173,6 +173,37 @@ def test_split_precision_matches_oracle(l, C, F):
     assert e32.max() < 1e-4
 
 
+# int8-slice form: FP64 operands as five 8-bit fixed-point digits on the int8 matrix cores,
+# exact int32 sums combined in FP64; the same 1e-9 gate as the split form.
+INT8_TOL = 1e-9
+
+
+@pytest.mark.parametrize("l,C,F", [(64, 16, 4), (128, 32, 8), (256, 64, 16), (64, 8, 12)])
+def test_int8_matches_oracle(l, C, F):
+    P = _plan(l, C, eps=1e-12)
+    beta = syn.coefficients(l, F, seed=0, power=1.5)
+    es = _rel(P.synth(_dev(beta), precision="int8").cpu().numpy(), oracle.synth(beta, l))
+    g = syn.grid(l, F, seed=1)
+    ea = _rel(P.analyze(_dev(g), precision="int8").cpu().numpy(), oracle.analyze(g, l))
+    r = syn.grid(l, F, seed=2)
+    ej = _rel(P.synth_adjoint(_dev(r), precision="int8").cpu().numpy(), oracle.synth_adjoint(r, l))
+    print(f"int8 l={l} C={C} F={F}: synth {es.max():.2e} analysis {ea.max():.2e} adjoint {ej.max():.2e}")
+    assert es.max() < INT8_TOL and ea.max() < INT8_TOL and ej.max() < INT8_TOL
+
+
+def test_int8_real_fields_and_plan_default():
+    from paper_0910_5435_amd import Plan
+
+    l, C, F = 64, 16, 8
+    P = Plan(l, eps=1e-12, leaf_width=C, kind="real", precision="int8")
+    beta = syn.coefficients(l, F, seed=3, kind="real", power=1.5)
+    ref = oracle.synth(beta, l, kind="real")
+    assert _rel(P.synth(_dev(beta)).cpu().numpy(), ref).max() < INT8_TOL
+    assert _rel(P.analyze(_dev(ref)).cpu().numpy(), beta).max() < INT8_TOL
+    r = syn.grid(l, F, seed=4, kind="real")
+    assert _rel(P.synth_adjoint(_dev(r)).cpu().numpy(), oracle.synth_adjoint(r, l, kind="real")).max() < INT8_TOL
+
+
 def test_prepare_and_split_only_plans():
     # A split-FP32 transform needs the split copies of the factors: SHT_ENOTREADY until
     # sht_plan_prepare derived them (the transforms themselves never allocate).  A split-only
@@ -196,7 +227,11 @@ def test_prepare_and_split_only_plans():
         return rc
 
     assert call(P, _lib.SHT_SPLIT32) == _lib.SHT_ENOTREADY
+    assert call(P, _lib.SHT_INT8) == _lib.SHT_ENOTREADY
     assert lib.sht_plan_prepare(P.handle, _lib.SHT_SPLIT32, None) == _lib.SHT_OK
+    assert call(P, _lib.SHT_INT8) == _lib.SHT_ENOTREADY
+    assert lib.sht_plan_prepare(P.handle, _lib.SHT_INT8, None) == _lib.SHT_OK
+    assert call(P, _lib.SHT_INT8) == _lib.SHT_OK
     assert call(P, _lib.SHT_SPLIT32) == _lib.SHT_OK
     ref = oracle.synth(beta.cpu().numpy(), l)
     assert _rel(grid.cpu().numpy(), ref).max() < SPLIT_TOL
