@@ -12,6 +12,7 @@ SHT_EHIP = -3
 SHT_EUNSUPPORTED = -4
 SHT_EINTERNAL = -5
 SHT_ENOTREADY = -6
+SHT_ECORRUPT = -7
 
 NOALLOC_SCRATCH_BYTES = 256 << 20  # SHT_NOALLOC_SCRATCH_BYTES of include/sht.h
 
@@ -36,6 +37,7 @@ class PlanOpts(ctypes.Structure):
         ("host_threads", ctypes.c_int),
         ("device", ctypes.c_int),
         ("split_only", ctypes.c_int),
+        ("cache_dir", ctypes.c_char_p),
     ]
 
 
@@ -57,6 +59,8 @@ class Stats(ctypes.Structure):
         ("eps", ctypes.c_double),
         ("device_bytes", ctypes.c_longlong),
         ("max_abs_t", ctypes.c_double),
+        ("cache_pairs_loaded", ctypes.c_longlong),
+        ("cache_rebuilt", ctypes.c_int),
     ]
 
 
@@ -136,6 +140,9 @@ SIGNATURES = {
     "sht_plan_tree": (_I, [_P, _I, _I, _IP, _IP]),
     "sht_bf_build": (_I, [_DP, _I, _I, _I, _I, _I, _D, ctypes.POINTER(_P)]),
     "sht_bf_destroy": (None, [_P]),
+    "sht_plan_cache_check": (_I, [ctypes.c_char_p, _I, _D, _I, ctypes.POINTER(_LL)]),
+    "sht_plan_cache_append": (_I, [ctypes.c_char_p, _I, _D, _I, _I, _P]),
+    "sht_plan_cache_read": (_I, [ctypes.c_char_p, _I, _D, _I, _I, ctypes.POINTER(_P)]),
     "sht_bf_info": (_I, [_P, _IP, _IP, _DP, _DP, ctypes.POINTER(_LL), ctypes.POINTER(_LL)]),
     "sht_bf_block": (_I, [_P, _I, _I, _I, _IP, _IP, ctypes.POINTER(_IP), ctypes.POINTER(_IP),
                           ctypes.POINTER(_DP)]),

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "interp_decomp.h"
+#include "plan_cache.h"
 #include "sht_internal.h"
 
 namespace sht {
@@ -327,6 +328,7 @@ void sht_default_opts(sht_plan_opts* o) {
   o->host_threads = 0;
   o->device = -1;
   o->split_only = 0;
+  o->cache_dir = nullptr;
 }
 
 int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nullptr, out); }
@@ -671,6 +673,58 @@ int sht_bf_build(const double* a, int rows, int cols, int lda, int leaf_width, i
 
 void sht_bf_destroy(sht_bf_t bf) { delete bf; }
 
+int sht_plan_cache_check(const char* cache_dir, int l, double eps, int leaf_width, long long* valid_pairs) {
+  if (valid_pairs) *valid_pairs = 0;
+  if (!cache_dir || l < 1 || leaf_width < 1 || !(eps > 0.0 && eps < 1.0)) return SHT_EINVAL;
+  CacheScan scan;
+  const int rc = cache_scan(cache_dir, l, eps, leaf_width, 4 * l, nullptr, nullptr, scan);
+  if (valid_pairs) *valid_pairs = scan.valid_pairs;
+  return rc;
+}
+
+int sht_plan_cache_read(const char* cache_dir, int l, double eps, int leaf_width, int mp, sht_bf_t* out) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  if (!cache_dir || l < 1 || leaf_width < 1 || !(eps > 0.0 && eps < 1.0) || mp < 0 || mp >= 4 * l)
+    return SHT_EINVAL;
+  try {
+    std::vector<PairShape> shapes(4 * l);
+    for (int q = 0; q < 4 * l; ++q) shapes[q] = pair_shape(l, leaf_width, q);
+    std::vector<BfTree> trees(4 * l);
+    CacheScan scan;
+    const int rc = cache_scan(cache_dir, l, eps, leaf_width, 4 * l, &shapes, &trees, scan);
+    if (scan.valid_pairs <= mp) return rc == SHT_ECORRUPT ? SHT_ECORRUPT : SHT_EINVAL;
+    sht_bf_s* bf = new sht_bf_s();
+    bf->tree = std::move(trees[mp]);
+    *out = bf;
+    return SHT_OK;
+  } catch (const std::bad_alloc&) {
+    return SHT_ENOMEM;
+  }
+}
+
+int sht_plan_cache_append(const char* cache_dir, int l, double eps, int leaf_width, int mp, sht_bf_t bf) {
+  if (!cache_dir || !bf || l < 1 || leaf_width < 1 || !(eps > 0.0 && eps < 1.0) || mp < 0 || mp >= 4 * l)
+    return SHT_EINVAL;
+  const PairShape sh = pair_shape(l, leaf_width, mp);
+  const BfTree& t = bf->tree;
+  if (t.rows() != sh.rows || t.cols() != sh.cols || t.L() != sh.L || t.C() != leaf_width || !t.complete())
+    return SHT_EINVAL;
+  CacheScan scan;
+  const int rc = cache_scan(cache_dir, l, eps, leaf_width, 4 * l, nullptr, nullptr, scan);
+  if (rc == SHT_ECORRUPT) return SHT_ECORRUPT;
+  if (mp != scan.valid_pairs) return SHT_EINVAL;
+  try {
+    CacheWriter w;
+    int e = w.open(cache_dir, l, eps, leaf_width, 4 * l, scan.valid_bytes);
+    if (e == SHT_OK) e = w.append(mp, t);
+    if (e == SHT_OK) e = w.flush();
+    return e;
+  } catch (const std::bad_alloc&) {
+    return SHT_ENOMEM;
+  }
+}
+
 int sht_bf_info(sht_bf_t bf, int* levels, int* k_max, double* k_avg, double* k_sd,
                 long long* factor_entries, long long* m_max_words) {
   if (!bf) return SHT_EINVAL;
@@ -721,6 +775,7 @@ const char* sht_strerror(int status) {
     case SHT_EUNSUPPORTED: return "unsupported configuration";
     case SHT_EINTERNAL: return "internal error";
     case SHT_ENOTREADY: return "plan not prepared for this precision (sht_plan_prepare)";
+    case SHT_ECORRUPT: return "plan cache file corrupt";
     default: return "unknown status";
   }
 }

@@ -385,4 +385,134 @@ void BfTree::merge(int t, int cc) {
   }
 }
 
+// ------------------------------------------------------------------ serialisation
+namespace {
+
+class ByteWriter {
+ public:
+  explicit ByteWriter(std::vector<unsigned char>& out) : out_(out) {}
+  template <typename T>
+  void put(const T& v) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+    out_.insert(out_.end(), b, b + sizeof(T));
+  }
+  template <typename T>
+  void put_vec(const std::vector<T>& v) {
+    put(static_cast<uint64_t>(v.size()));
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(v.data());
+    out_.insert(out_.end(), b, b + v.size() * sizeof(T));
+  }
+
+ private:
+  std::vector<unsigned char>& out_;
+};
+
+class ByteReader {
+ public:
+  ByteReader(const unsigned char* p, size_t n) : p_(p), n_(n) {}
+  template <typename T>
+  bool get(T& v) {
+    if (n_ - off_ < sizeof(T)) return false;
+    std::memcpy(&v, p_ + off_, sizeof(T));
+    off_ += sizeof(T);
+    return true;
+  }
+  template <typename T>
+  bool get_vec(std::vector<T>& v, uint64_t max_count) {
+    uint64_t c = 0;
+    if (!get(c) || c > max_count || (n_ - off_) / sizeof(T) < c) return false;
+    v.resize(c);
+    std::memcpy(v.data(), p_ + off_, c * sizeof(T));
+    off_ += c * sizeof(T);
+    return true;
+  }
+  bool done() const { return off_ == n_; }
+
+ private:
+  const unsigned char* p_;
+  size_t n_, off_ = 0;
+};
+
+}  // namespace
+
+void BfTree::save(std::vector<unsigned char>& out) const {
+  ByteWriter w(out);
+  w.put(static_cast<int32_t>(rows_));
+  w.put(static_cast<int32_t>(cols_));
+  w.put(static_cast<int32_t>(C_));
+  w.put(static_cast<int32_t>(L_));
+  w.put(eps_);
+  w.put(static_cast<int32_t>(k_max));
+  w.put(static_cast<int64_t>(n_ids));
+  w.put(sum_k);
+  w.put(sum_k2);
+  w.put(static_cast<int64_t>(factor_entries));
+  w.put(static_cast<int64_t>(m_max_words));
+  w.put(max_abs_t);
+  for (int t = 0; t <= L_; ++t)
+    for (const BfBlock& b : blocks_[t]) {
+      w.put(static_cast<int32_t>(b.k));
+      w.put(static_cast<int32_t>(b.K));
+      w.put_vec(b.skel);
+      w.put_vec(b.red);
+      w.put_vec(b.T);
+    }
+  for (const BfFinal& f : finals_) {
+    w.put(static_cast<int32_t>(f.row0));
+    w.put(static_cast<int32_t>(f.h));
+    w.put(static_cast<int32_t>(f.k));
+    w.put_vec(f.S);
+    w.put_vec(f.cols);
+  }
+}
+
+bool BfTree::load(const unsigned char* p, size_t n, int rows, int cols, int C, int L, double eps) {
+  ByteReader r(p, n);
+  int32_t rr = 0, cc = 0, c = 0, l = 0, km = 0;
+  double e = 0.0;
+  int64_t nid = 0, fe = 0, mw = 0;
+  if (!r.get(rr) || !r.get(cc) || !r.get(c) || !r.get(l) || !r.get(e)) return false;
+  if (rr != rows || cc != cols || c != C || l != L || e != eps) return false;
+  init(rows, cols, C, L, eps);
+  if (!r.get(km) || !r.get(nid) || !r.get(sum_k) || !r.get(sum_k2) || !r.get(fe) || !r.get(mw) || !r.get(max_abs_t))
+    return false;
+  k_max = km;
+  n_ids = nid;
+  factor_entries = fe;
+  m_max_words = mw;
+  const uint64_t cap = static_cast<uint64_t>(rows + 1) * (cols + 1) + 16;
+  long long entries = 0;
+  for (int t = 0; t <= L_; ++t)
+    for (BfBlock& b : blocks_[t]) {
+      int32_t k = 0, K = 0;
+      if (!r.get(k) || !r.get(K) || !r.get_vec(b.skel, cap) || !r.get_vec(b.red, cap) || !r.get_vec(b.T, cap))
+        return false;
+      b.k = k;
+      b.K = K;
+      if (k < 0 || K < k || b.skel.size() != static_cast<size_t>(k) || b.red.size() != static_cast<size_t>(K - k) ||
+          (!b.T.empty() && b.T.size() != static_cast<size_t>(k) * (K - k)))
+        return false;
+      for (int v : b.skel)
+        if (v < 0 || v >= K) return false;
+      for (int v : b.red)
+        if (v < 0 || v >= K) return false;
+      entries += static_cast<long long>(b.T.size());
+    }
+  for (int q = 0; q < (1 << L_); ++q) {
+    BfFinal& f = finals_[q];
+    int32_t row0 = 0, h = 0, k = 0;
+    if (!r.get(row0) || !r.get(h) || !r.get(k) || !r.get_vec(f.S, cap) || !r.get_vec(f.cols, cap)) return false;
+    f.row0 = row0;
+    f.h = h;
+    f.k = k;
+    if (row0 != row_lo_[L_][q] || h != row_h_[L_][q] || k < 0 || f.cols.size() != static_cast<size_t>(k) ||
+        (!f.S.empty() && f.S.size() != static_cast<size_t>(h) * k))
+      return false;
+    entries += static_cast<long long>(f.S.size());
+  }
+  if (entries != factor_entries || !r.done()) return false;
+  next_leaf_ = 1 << L_;  // complete: no pending state
+  return true;
+}
+
 }  // namespace sht

@@ -81,6 +81,12 @@ class BfTree {
 
   // rank statistics over every non-empty block (leaves and merges; a padded tree also has
   // empty slots, which k_max ignores by construction and n_ids / sum_k skip)
+  // Serialised form of a complete tree (one record of the plan cache): shape, statistics,
+  // every block and final skeleton.  load() rebuilds a tree that packs to the same factors;
+  // it returns false (leaving the tree unusable) for a malformed or mismatched record.
+  void save(std::vector<unsigned char>& out) const;
+  bool load(const unsigned char* p, size_t n, int rows, int cols, int C, int L, double eps);
+
   int k_max = 0;
   long long n_ids = 0;
   double sum_k = 0.0, sum_k2 = 0.0;

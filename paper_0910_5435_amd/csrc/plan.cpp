@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "interp_decomp.h"
+#include "plan_cache.h"
 #include "sht_internal.h"
 
 namespace sht {
@@ -158,19 +159,32 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   P->n_cols.assign(npairs, 0);
   P->levels.assign(npairs, 0);
   int Lmax = 0;
-  for (int m = 0; m < L2; ++m) {
-    const int n = L2 - m;
-    const int n0 = (n + 1) / 2, n1 = n / 2;
-    const int L = butterfly_depth(n0, C);
-    P->n_cols[2 * m] = n0;
-    P->n_cols[2 * m + 1] = n1;
-    P->levels[2 * m] = P->levels[2 * m + 1] = L;
-    Lmax = std::max(Lmax, L);
+  std::vector<PairShape> shapes(npairs);
+  for (int mp = 0; mp < npairs; ++mp) {
+    shapes[mp] = pair_shape(l, C, mp);
+    P->n_cols[mp] = shapes[mp].cols;
+    P->levels[mp] = shapes[mp].L;
+    Lmax = std::max(Lmax, shapes[mp].L);
   }
   P->Lmax = Lmax;
 
   std::vector<BfTree> trees(npairs);
-  for (int mp = 0; mp < npairs; ++mp)
+  // Plan cache: the butterflies of an intact prefix of pairs come from disk; the rest are
+  // built below and appended batch by batch (a corrupt or foreign tail is cut off first).
+  int nvalid = 0;
+  CacheWriter cache;
+  if (o.cache_dir) {
+    CacheScan scan;
+    (void)cache_scan(o.cache_dir, l, P->eps, C, npairs, &shapes, &trees, scan);
+    nvalid = scan.valid_pairs;
+    P->stats.cache_pairs_loaded = nvalid;
+    P->stats.cache_rebuilt = scan.corrupt ? 1 : 0;
+    if (nvalid < npairs || scan.corrupt) {
+      const int rc = cache.open(o.cache_dir, l, P->eps, C, npairs, scan.corrupt && nvalid == 0 ? 0 : scan.valid_bytes);
+      if (rc != SHT_OK) return rc;
+    }
+  }
+  for (int mp = nvalid; mp < npairs; ++mp)
     trees[mp].init(l, P->n_cols[mp], C, P->levels[mp], P->eps);
 
   // Device-side column generation, batch by batch.
@@ -203,6 +217,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   int err = SHT_OK;
   for (int b0 = 0; b0 < npairs && err == SHT_OK; b0 += batch) {
     const int nb = std::min(batch, npairs - b0);
+    if (b0 + nb <= nvalid) continue;  // every butterfly of the batch came from the cache
     std::vector<int> hm(nb), hp(nb), hn(nb);
     int leaves = 0;
     for (int b = 0; b < nb; ++b) {
@@ -238,7 +253,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
       std::atomic<int> bad{0};
       parallel_for(nb, nthreads, [&](int b) {
         BfTree& tr = trees[b0 + b];
-        if (c >= (1 << tr.L())) return;
+        if (b0 + b < nvalid || c >= (1 << tr.L())) return;
         try {
           tr.add_leaf(c, host_chunk + static_cast<size_t>(b) * chunk_doubles, l);
         } catch (const std::bad_alloc&) {
@@ -252,6 +267,10 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
         err = bad;
         break;
       }
+    }
+    if (err == SHT_OK && cache.is_open()) {
+      for (int mp = std::max(b0, nvalid); mp < b0 + nb && err == SHT_OK; ++mp) err = cache.append(mp, trees[mp]);
+      if (err == SHT_OK) err = cache.flush();
     }
   }
   if (err != SHT_OK) return err;

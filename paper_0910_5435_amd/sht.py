@@ -56,7 +56,7 @@ class Plan:
     """Butterfly SHT plan for bandlimit l (degrees 0..2l-1) on one GPU."""
 
     def __init__(self, l, eps=1e-13, leaf_width=64, precision="fp64", kind="complex",
-                 host_threads=0, device=None, split_only=False):
+                 host_threads=0, device=None, split_only=False, cache_dir=None):
         lib = L.load()
         opts = L.PlanOpts()
         lib.sht_default_opts(ctypes.byref(opts))
@@ -65,6 +65,8 @@ class Plan:
         opts.field_kind = KINDS[kind]
         opts.host_threads = int(host_threads)
         opts.split_only = 1 if split_only else 0
+        self._cache_dir = None if cache_dir is None else str(cache_dir).encode()
+        opts.cache_dir = self._cache_dir
         if device is None:
             opts.device = -1
         else:
@@ -338,6 +340,20 @@ class Batch:
                            "queues": i.config.queues}}
 
 
+def plan_cache_check(cache_dir, l, eps, leaf_width=64):
+    """(status, intact leading records) of the plan cache file of (l, eps, leaf_width):
+    status 0 (every record present intact), SHT_ECORRUPT or SHT_EINVAL (no file); host only."""
+    n = ctypes.c_longlong()
+    rc = L.load().sht_plan_cache_check(str(cache_dir).encode(), int(l), float(eps), int(leaf_width), ctypes.byref(n))
+    return rc, n.value
+
+
+def plan_cache_append(cache_dir, l, eps, leaf_width, mp, butterfly):
+    """Append a host-built Butterfly of pair mp = 2m + p as the next plan cache record."""
+    L.check(L.load().sht_plan_cache_append(str(cache_dir).encode(), int(l), float(eps), int(leaf_width), int(mp),
+                                           butterfly._h), "sht_plan_cache_append")
+
+
 def gauss_jacobi_rule(m, n, parity=0):
     """Nodes x (ascending, positive) and weights lambda = rho (1 - x^2)^m (parity 0) or
     sigma (1 - x^2)^m (parity 1) of the per-order quadratures of Section 4 (Lemma
@@ -372,6 +388,27 @@ class Butterfly:
                                  int(levels), float(eps), ctypes.byref(h)), "sht_bf_build")
         self._h = h
         self.rows, self.cols, self.C = rows, cols, int(leaf_width)
+        self._read_info()
+
+    @classmethod
+    def from_plan_cache(cls, cache_dir, l, eps, leaf_width, mp):
+        """The butterfly of pair mp = 2m + p read back from a plan cache file (host only)."""
+        h = ctypes.c_void_p()
+        L.check(L.load().sht_plan_cache_read(str(cache_dir).encode(), int(l), float(eps), int(leaf_width), int(mp),
+                                             ctypes.byref(h)), "sht_plan_cache_read")
+        self = cls.__new__(cls)
+        self._h = h
+        self._a = None
+        self.C = int(leaf_width)
+        self.rows = int(l)
+        m, n = mp // 2, 2 * int(l) - mp // 2
+        self.cols = (n + 1) // 2 if mp % 2 == 0 else n // 2
+        self._read_info()
+        return self
+
+    def _read_info(self):
+        lib = L.load()
+        h = self._h
         lv, km = ctypes.c_int(), ctypes.c_int()
         ka, ks = ctypes.c_double(), ctypes.c_double()
         fe, mm = ctypes.c_longlong(), ctypes.c_longlong()

@@ -245,6 +245,51 @@ def test_prepare_and_split_only_plans():
     assert ei.value.status == _lib.SHT_EINVAL
 
 
+def test_plan_cache_round_trip_resume_and_rebuild(tmp_path):
+    # A plan built with a cache directory writes every pair's butterfly; the next plan reads
+    # them all back and transforms bit for bit like the first; a cache cut at a record boundary
+    # resumes there, and one with a flipped byte is cut at that record and rebuilt.
+    from paper_0910_5435_amd import Plan, _lib, plan_cache_check
+
+    l, C, eps, F = 64, 16, 1e-13, 4
+    npairs = 4 * l
+    beta = _dev(syn.coefficients(l, F, seed=9))
+    grid = _dev(syn.grid(l, F, seed=10))
+
+    def build():
+        P = Plan(l, eps=eps, leaf_width=C, cache_dir=tmp_path)
+        st = P.stats()
+        out = (P.synth(beta).cpu().numpy(), P.analyze(grid).cpu().numpy())
+        P.close()
+        return st, out
+
+    st0, ref = build()
+    assert st0["cache_pairs_loaded"] == 0 and st0["cache_rebuilt"] == 0
+    assert plan_cache_check(tmp_path, l, eps, C) == (_lib.SHT_OK, npairs)
+    st1, got = build()
+    assert st1["cache_pairs_loaded"] == npairs and st1["factor_entries"] == st0["factor_entries"]
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    path = next(p for p in tmp_path.iterdir() if p.suffix == ".cache")
+    data = bytearray(path.read_bytes())
+    offs, off = [], 36
+    while off < len(data):
+        offs.append(off)
+        off += 16 + int.from_bytes(data[off + 4:off + 12], "little")
+    path.write_bytes(bytes(data[:offs[100]]))  # an interrupted build: 100 pairs done
+    st2, got = build()
+    assert st2["cache_pairs_loaded"] == 100 and st2["cache_rebuilt"] == 0
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    assert plan_cache_check(tmp_path, l, eps, C) == (_lib.SHT_OK, npairs)
+    data = bytearray(path.read_bytes())
+    data[offs[37] + 40] ^= 0x04
+    path.write_bytes(bytes(data))
+    assert plan_cache_check(tmp_path, l, eps, C) == (_lib.SHT_ECORRUPT, 37)
+    st3, got = build()
+    assert st3["cache_pairs_loaded"] == 37 and st3["cache_rebuilt"] == 1
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    assert plan_cache_check(tmp_path, l, eps, C) == (_lib.SHT_OK, npairs)
+
+
 def test_split_precision_real_fields_and_adjoint():
     l, C, F = 64, 16, 8
     P = _plan(l, C, eps=1e-12, kind="real")
