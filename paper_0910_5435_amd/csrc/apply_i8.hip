@@ -105,6 +105,14 @@ __device__ __forceinline__ void load_a8(const int8_t* __restrict__ base, long lo
   for (int s = 0; s < kI8Dig; ++s) a[s] = p[s * 64];
 }
 
+// Row exponents of the four rows 16 m + 4 lr + v (v = 0..3) a lane's accumulator elements
+// belong to: one 8-byte load (exponent lists are padded to whole 16-row tiles).
+__device__ __forceinline__ int4 load_ex4(const int16_t* __restrict__ base, int m, int lr) {
+  const int2 w = *reinterpret_cast<const int2*>(base + m * 16 + 4 * lr);
+  return make_int4((w.x << 16) >> 16, w.x >> 16, (w.y << 16) >> 16, w.y >> 16);
+}
+__device__ __forceinline__ int ex_of(const int4& e, int v) { return v == 0 ? e.x : v == 1 ? e.y : v == 2 ? e.z : e.w; }
+
 // B operand of chunk q, column tile n from a digit set in LDS (NTL column tiles).
 template <int NTL>
 __device__ __forceinline__ void load_b8(const unsigned char* set, int q, int n, int lane, v4i (&b)[kI8Dig]) {
@@ -119,7 +127,12 @@ __device__ void i8_col_exps(int n, Fetch&& fetch, double* red, int* ecol) {
   constexpr int G = 256 / NT;
   const int c = threadIdx.x % NT, g = threadIdx.x / NT;
   double mx = 0.0;
-  for (int j = g; j < n; j += G) mx = fmax(mx, fabs(fetch(j, c)));
+  int j = g;
+  for (; j + 3 * G < n; j += 4 * G) {  // four independent loads in flight (global sources)
+    const double a0 = fetch(j, c), a1 = fetch(j + G, c), a2 = fetch(j + 2 * G, c), a3 = fetch(j + 3 * G, c);
+    mx = fmax(mx, fmax(fmax(fabs(a0), fabs(a1)), fmax(fabs(a2), fabs(a3))));
+  }
+  for (; j < n; j += G) mx = fmax(mx, fabs(fetch(j, c)));
   red[threadIdx.x] = mx;
   __syncthreads();
   if (threadIdx.x < NT) {
@@ -252,12 +265,17 @@ k_level_synth_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
   const int lc = lane & 15, lr = lane >> 4;
   const int nm[2] = {(k0 + 15) >> 4, (k1 + 15) >> 4};
   const int nqs[2] = {(K - k0 + 63) >> 6, (K - k1 + 63) >> 6};
-  auto load_unit = [&](int o, int mt, int q, v4i (&a)[kI8Dig]) {
-    if (q < nqs[o]) load_a8(dig + (o ? tk.i8[1].dig[0] : tk.i8[0].dig[0]), mt, q, nqs[o], lane, a);
+  // a unit's A digits; with the tile's first chunk also its row exponents
+  auto load_unit = [&](int o, int mt, int q, v4i (&a)[kI8Dig], int4& e) {
+    if (q < nqs[o]) {
+      load_a8(dig + (o ? tk.i8[1].dig[0] : tk.i8[0].dig[0]), mt, q, nqs[o], lane, a);
+      if (q == 0) e = load_ex4(dex + (o ? tk.i8[1].ex[0] : tk.i8[0].ex[0]), mt, lr);
+    }
   };
   v4i an[kI8Dig];
-  if (wave < nm[0]) load_unit(0, wave, 0, an);
-  else if (nouts > 1 && wave < nm[1]) load_unit(1, wave, 0, an);
+  int4 en = make_int4(0, 0, 0, 0), et = en;
+  if (wave < nm[0]) load_unit(0, wave, 0, an, en);
+  else if (nouts > 1 && wave < nm[1]) load_unit(1, wave, 0, an, en);
   __syncthreads();
   i8_col_exps<NT>(K, [&](int j, int c) { return xs[j * LD + c]; }, red_s, ecol);  // (also publishes ix)
   int ec[NTL];
@@ -271,7 +289,6 @@ k_level_synth_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
     __syncthreads();
     const int nq = nqs[o];
     const uint16_t* skel = ix + o * K;
-    const int16_t* er = dex + (o ? tk.i8[1].ex[0] : tk.i8[0].ex[0]);
     double* ob = out + static_cast<long long>(o ? tk.out_row[1] : tk.out_row[0]) * R + c0;
     I8Acc acc[NTL];
     for (int mt = wave, q = 0; mt < nm[o];) {
@@ -283,8 +300,9 @@ k_level_synth_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
         mt2 = mt + 4;
         q2 = 0;
       }
-      if (mt2 < nm[o]) load_unit(o, mt2, q2, an);
-      else if (o + 1 < nouts && wave < nm[1]) load_unit(1, wave, 0, an);  // the next output's first unit
+      if (q == 0) et = en;
+      if (mt2 < nm[o]) load_unit(o, mt2, q2, an, en);
+      else if (o + 1 < nouts && wave < nm[1]) load_unit(1, wave, 0, an, en);  // the next output's first unit
       if (q == 0) {
 #pragma unroll
         for (int n = 0; n < NTL; ++n) i8_zero(acc[n]);
@@ -302,7 +320,7 @@ k_level_synth_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
         for (int v = 0; v < 4; ++v) {
           const int row = mt * 16 + 4 * lr + v;
           if (row < k) {
-            const int erow = nq > 0 ? er[row] : 0;
+            const int erow = ex_of(et, v);
             const double* xr = xs + static_cast<int>(skel[row]) * LD;
 #pragma unroll
             for (int n = 0; n < NTL; ++n) {
@@ -322,8 +340,8 @@ k_level_synth_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
 // in = sum_o (w_o at rows skel_o) + (T_o^T w_o at rows red_o) into an FP64 block in LDS, one
 // output at a time: every row gets exactly one term from each output, so output 0 stores its
 // terms and output 1 adds its own, with no clearing and no atomics.  LDS: the K x (NT + 2) FP64
-// block, the digit set of the current output's w_o (setb bytes), then the index lists.  w_o is
-// read from global memory (three passes over k_o rows, the later ones from cache).
+// block, the current output's w_o staged with batched loads (max(k_0, k_1) x (NT + 2) FP64),
+// its digit set (setb bytes), then the index lists.
 template <int NT>
 __global__ void __launch_bounds__(256, 2)
 k_level_trans_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, const int8_t* __restrict__ dig,
@@ -344,7 +362,8 @@ k_level_trans_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
   const int k0 = tk.k[0], k1 = nouts > 1 ? tk.k[1] : 0;
   const long long c0 = static_cast<long long>(blk) * NT;
   double* acc_l = reinterpret_cast<double*>(lds8);
-  unsigned char* set = lds8 + static_cast<size_t>(K) * LD * 8;
+  double* wl = acc_l + K * LD;  // the current output's w_o (k_o rows)
+  unsigned char* set = reinterpret_cast<unsigned char*>(wl + (k0 > k1 ? k0 : k1) * LD);
   uint16_t* ix = reinterpret_cast<uint16_t*>(set + setb);
   for (int o = 0; o < nouts; ++o)
     for (int e = threadIdx.x; e < K; e += 256) ix[o * K + e] = idx[tk.idx[o] + e];
@@ -353,30 +372,35 @@ k_level_trans_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
   const int lc = lane & 15, lr = lane >> 4;
   const int nm[2] = {(K - k0 + 15) >> 4, nouts > 1 ? (K - k1 + 15) >> 4 : 0};
   const int nqs[2] = {(k0 + 63) >> 6, (k1 + 63) >> 6};
-  auto load_unit = [&](int o, int mt, int q, v4i (&a)[kI8Dig]) {
-    if (q < nqs[o]) load_a8(dig + (o ? tk.i8[1].dig[1] : tk.i8[0].dig[1]), mt, q, nqs[o], lane, a);
+  auto load_unit = [&](int o, int mt, int q, v4i (&a)[kI8Dig], int4& e) {
+    if (q < nqs[o]) {
+      load_a8(dig + (o ? tk.i8[1].dig[1] : tk.i8[0].dig[1]), mt, q, nqs[o], lane, a);
+      if (q == 0) e = load_ex4(dex + (o ? tk.i8[1].ex[1] : tk.i8[0].ex[1]), mt, lr);
+    }
   };
   v4i an[kI8Dig];
-  if (wave < nm[0]) load_unit(0, wave, 0, an);
-  else if (wave < nm[1]) load_unit(1, wave, 0, an);
+  int4 en = make_int4(0, 0, 0, 0), et = en;
+  if (wave < nm[0]) load_unit(0, wave, 0, an, en);
+  else if (wave < nm[1]) load_unit(1, wave, 0, an, en);
   for (int o = 0; o < nouts; ++o) {
     const int k = o ? k1 : k0;
-    const double* w = win + static_cast<long long>(o ? tk.out_row[1] : tk.out_row[0]) * R + c0;
-    auto fw = [&](int j, int c) { return w[static_cast<long long>(j) * R + c]; };
-    i8_col_exps<NT>(k, fw, red_s, ecol);  // (its first barrier also publishes ix / ends output 0)
+    // w_o into LDS with batched loads (the output-0 units never read this region)
+    stage_rows<NT, LD>(win + static_cast<long long>(o ? tk.out_row[1] : tk.out_row[0]) * R + c0, k, R, wl);
+    __syncthreads();  // (also publishes ix, and ends output 0's units)
+    auto fw = [&](int j, int c) { return wl[j * LD + c]; };
+    i8_col_exps<NT>(k, fw, red_s, ecol);
     i8_cut<NT>(k, fw, ecol, set);
     // identity part: w_o at the skeleton rows (output 0 stores, output 1 adds)
     const uint16_t* skel = ix + o * K;
     for (int e = threadIdx.x; e < k * NT; e += 256) {
       double* d = acc_l + static_cast<int>(skel[e / NT]) * LD + e % NT;
-      const double val = w[static_cast<long long>(e / NT) * R + e % NT];
+      const double val = wl[(e / NT) * LD + e % NT];
       *d = o ? *d + val : val;
     }
     __syncthreads();
     const int nq = nqs[o];
     const int nr = K - k;
     const uint16_t* red = ix + o * K + k;
-    const int16_t* er = dex + (o ? tk.i8[1].ex[1] : tk.i8[0].ex[1]);
     int ec[NTL];
 #pragma unroll
     for (int n = 0; n < NTL; ++n) ec[n] = ecol[n * 16 + lc];
@@ -390,8 +414,9 @@ k_level_trans_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
         mt2 = mt + 4;
         q2 = 0;
       }
-      if (mt2 < nm[o]) load_unit(o, mt2, q2, an);
-      else if (o + 1 < nouts && wave < nm[1]) load_unit(1, wave, 0, an);
+      if (q == 0) et = en;
+      if (mt2 < nm[o]) load_unit(o, mt2, q2, an, en);
+      else if (o + 1 < nouts && wave < nm[1]) load_unit(1, wave, 0, an, en);
       if (q == 0) {
 #pragma unroll
         for (int n = 0; n < NTL; ++n) i8_zero(acc[n]);
@@ -409,7 +434,7 @@ k_level_trans_i8(const LevelTask* __restrict__ tasks, long long ntasks, int nblk
         for (int v = 0; v < 4; ++v) {
           const int j = mt * 16 + 4 * lr + v;
           if (j < nr) {
-            const int ej = nq > 0 ? er[j] : 0;
+            const int ej = ex_of(et, v);
             double* dst = acc_l + static_cast<int>(red[j]) * LD;
 #pragma unroll
             for (int n = 0; n < NTL; ++n) {
@@ -468,12 +493,18 @@ k_final_synth_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
   const int nq0 = (k0 + 63) >> 6, nq1 = (k1 + 63) >> 6;
   const int nu = nq0 + nq1;  // units per tile: parity 0 chunks, then parity 1 chunks
   const int nm = (h + 15) >> 4;
-  auto load_unit = [&](int mt, int u, v4i (&a)[kI8Dig]) {
+  // a unit's A digits; with a tile's first unit also the row exponents of both parities
+  auto load_unit = [&](int mt, int u, v4i (&a)[kI8Dig], int4& e0, int4& e1) {
+    if (u == 0) {
+      if (k0 > 0) e0 = load_ex4(dex + ft.i8[0].ex[0], mt, lr);
+      if (k1 > 0) e1 = load_ex4(dex + ft.i8[1].ex[0], mt, lr);
+    }
     if (u < nq0) load_a8(dig + ft.i8[0].dig[0], mt, u, nq0, lane, a);
     else if (u < nu) load_a8(dig + ft.i8[1].dig[0], mt, u - nq0, nq1, lane, a);
   };
   v4i an[kI8Dig];
-  if (wave < nm) load_unit(wave, 0, an);
+  int4 en0 = make_int4(0, 0, 0, 0), en1 = en0, et0 = en0, et1 = en0;
+  if (wave < nm) load_unit(wave, 0, an, en0, en1);
   for (int p = 0; p < 2; ++p) {
     const double* v = V + static_cast<long long>(p ? ft.in_row[1] : ft.in_row[0]) * R + c0;
     auto fv = [&](int j, int c) { return v[static_cast<long long>(j) * R + c]; };
@@ -492,7 +523,11 @@ k_final_synth_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
       mt2 = mt + 4;
       u2 = 0;
     }
-    if (mt2 < nm) load_unit(mt2, u2, an);
+    if (u == 0) {
+      et0 = en0;
+      et1 = en1;
+    }
+    if (mt2 < nm) load_unit(mt2, u2, an, en0, en1);
     if (u == 0) {
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
@@ -522,8 +557,7 @@ k_final_synth_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
         if (ii < h) {
           const int row = ft.row0 + ii;
           const double sc = invD[row];
-          const int e0 = k0 > 0 ? dex[ft.i8[0].ex[0] + ii] : 0;
-          const int e1 = k1 > 0 ? dex[ft.i8[1].ex[0] + ii] : 0;
+          const int e0 = ex_of(et0, v), e1 = ex_of(et1, v);
           double* yp = Y + (ybase + l + row) * R + c0;
           double* ym = Y + (ybase + l - 1 - row) * R + c0;
 #pragma unroll
@@ -578,15 +612,17 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lc = lane & 15, lr = lane >> 4;
   const int nm0 = (k0 + 15) >> 4, ntot = nm0 + ((k1 + 15) >> 4);
-  auto load_unit = [&](int tq, int cq, v4i (&a)[kI8Dig]) {
+  auto load_unit = [&](int tq, int cq, v4i (&a)[kI8Dig], int4& e) {
     const int p = tq < nm0 ? 0 : 1;
     load_a8(dig + (p ? ft.i8[1].dig[1] : ft.i8[0].dig[1]), p ? tq - nm0 : tq, cq, qh, lane, a);
+    e = load_ex4(dex + (p ? ft.i8[1].ex[1] : ft.i8[0].ex[1]), p ? tq - nm0 : tq, lr);
   };
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     const int nq = (ih + 63) >> 6;
     v4i an[kI8Dig];
-    if (wave < ntot) load_unit(wave, i0 / 64, an);
+    int4 en = make_int4(0, 0, 0, 0), et = en;
+    if (wave < ntot) load_unit(wave, i0 / 64, an, en);
     __syncthreads();
     staged<double2, 2>(
         ih * NT,
@@ -620,7 +656,8 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
         tq2 = tq + 4;
         cq2 = 0;
       }
-      if (tq2 < ntot) load_unit(tq2, i0 / 64 + cq2, an);
+      if (cq == 0) et = en;
+      if (tq2 < ntot) load_unit(tq2, i0 / 64 + cq2, an, en);
       if (cq == 0) {
 #pragma unroll
         for (int n = 0; n < NTL; ++n) i8_zero(acc[n]);
@@ -633,7 +670,6 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
       }
       if (cq2 == 0) {
         const int kp = p ? k1 : k0;
-        const int16_t* er = dex + (p ? ft.i8[1].ex[1] : ft.i8[0].ex[1]);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a_ = mt * 16 + 4 * lr + v;
@@ -641,7 +677,7 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
             double* srow = sums + (p ? k0 + a_ : a_) * NT;
 #pragma unroll
             for (int n = 0; n < NTL; ++n)
-              srow[n * 16 + lc] += i8_value(acc[n], v, er[a_], ecol[p][n * 16 + lc]);
+              srow[n * 16 + lc] += i8_value(acc[n], v, ex_of(et, v), ecol[p][n * 16 + lc]);
           }
         }
       }
@@ -728,8 +764,10 @@ hipError_t launch_level_i8(const sht_plan_s* P, int step, bool transpose, const 
     const int K = lc.maxK;
     // contraction length per output: synthesis K - k (red rows), transposed k (w rows)
     const int kd = transpose ? lc.maxk : lc.maxnr;
-    // FP64 block of K rows (the staged input, or the transposed sums), one digit set, indices
-    auto need = [&](int nt) { return set_bytes(kd, nt) + 4LL * K + static_cast<long long>(K) * (nt + 2) * 8; };
+    // FP64 block of K rows (the staged input, or the transposed sums plus one staged output
+    // vector), one digit set, indices
+    const long long rows = transpose ? static_cast<long long>(K) + lc.maxk : K;
+    auto need = [&](int nt) { return set_bytes(kd, nt) + 4LL * K + rows * (nt + 2) * 8; };
     const int NT = pick_nt(R, need);
     if (NT == 0) return hipErrorInvalidConfiguration;
     const int setb = static_cast<int>(set_bytes(kd, NT));
