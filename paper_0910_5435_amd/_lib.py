@@ -149,6 +149,11 @@ SIGNATURES = {
     "sht_bf_final": (_I, [_P, _I, _IP, _IP, _IP, ctypes.POINTER(_DP), ctypes.POINTER(_IP)]),
     "sht_gj_rule": (_I, [_I, _I, _I, _DP, _DP]),
     "sht_gj_matrix": (_I, [_I, _I, _I, _DP, _I]),
+    "sht_order_plan": (_I, [_I, _D, ctypes.POINTER(PlanOpts), ctypes.POINTER(_P)]),
+    "sht_order_rows": (_LL, [_P]),
+    "sht_order_layout": (_I, [_P, _I, _I, ctypes.POINTER(_LL), _IP]),
+    "sht_order_workspace_bytes": (_S, [_P, _I]),
+    "sht_order_apply": (_I, [_P, _P, _P, _I, _I, _P, _S, _P]),
     "sht_profile_enable": (_I, [_P, _I]),
     "sht_profile_reset": (_I, [_P]),
     "sht_profile_count": (_I, [_P]),

@@ -121,6 +121,7 @@ class DeviceScope {
 int check_call(const sht_plan_s* P, int precision, const void* a, const void* b, int F, void* ws,
                size_t wsb) {
   if (!P || !a || !b || F < 1 || !ws) return SHT_EINVAL;
+  if (P->maps) return SHT_EINVAL;  // a plan of the per-order maps has no SHT
   if (precision < SHT_FP64 || precision > SHT_INT8) return SHT_EINVAL;
   // the split, FP32 and int8 forms run on the matrix-core kernels only (R a multiple of 16),
   // on factor copies that sht_plan_prepare (or a plan built for that precision) derived
@@ -333,19 +334,10 @@ void sht_default_opts(sht_plan_opts* o) {
 
 int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nullptr, out); }
 
-int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
-  if (!out) return SHT_EINVAL;
-  *out = nullptr;
-  sht_plan_opts o;
-  sht_default_opts(&o);
-  if (opts) o = *opts;
-  if (o.leaf_width == 0) o.leaf_width = 64;
-  if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 1 || o.leaf_width > 4096)
-    return SHT_EINVAL;
-  if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
-  if (o.field_kind != SHT_COMPLEX && o.field_kind != SHT_REAL) return SHT_EINVAL;
-  if (o.split_only && o.precision == SHT_FP64) return SHT_EINVAL;
-  if (!pow2(l) || l > 2048) return SHT_EUNSUPPORTED;
+namespace {
+
+// Builds and uploads a plan (validated options); maps: the per-order maps of Section 4.
+int make_plan(int l, double eps, const sht_plan_opts& o, bool maps, sht_plan_t* out) {
   int dev = o.device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return SHT_EHIP;
   DeviceScope ds(dev);
@@ -358,6 +350,7 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   P->device = dev;
   P->precision = o.precision;
   P->kind = o.field_kind;
+  P->maps = maps;
   int rc;
   try {
     rc = build_plan(P, o);
@@ -387,9 +380,99 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   return SHT_OK;
 }
 
+}  // namespace
+
+int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  sht_plan_opts o;
+  sht_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.leaf_width == 0) o.leaf_width = 64;
+  if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 1 || o.leaf_width > 4096)
+    return SHT_EINVAL;
+  if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
+  if (o.field_kind != SHT_COMPLEX && o.field_kind != SHT_REAL) return SHT_EINVAL;
+  if (o.split_only && o.precision == SHT_FP64) return SHT_EINVAL;
+  if (!pow2(l) || l > 2048) return SHT_EUNSUPPORTED;
+  return make_plan(l, eps, o, false, out);
+}
+
+int sht_order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  sht_plan_opts o;
+  sht_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.leaf_width == 0) o.leaf_width = 64;
+  if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 2 || o.leaf_width > 4096) return SHT_EINVAL;
+  if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
+  if (l > 2048 || o.precision != SHT_FP64 || o.split_only || o.cache_dir) return SHT_EUNSUPPORTED;
+  return make_plan(l, eps, o, true, out);
+}
+
+long long sht_order_rows(sht_plan_t plan) {
+  if (!plan || !plan->maps) return SHT_EINVAL;
+  return plan->rows_in;
+}
+
+int sht_order_layout(sht_plan_t plan, int m, int p, long long* row0, int* n) {
+  if (!plan || !plan->maps || m < 0 || m >= 2 * plan->l || (p != 0 && p != 1)) return SHT_EINVAL;
+  if (row0) *row0 = plan->in_base[2 * m + p];
+  if (n) *n = plan->n_cols[2 * m + p];
+  return SHT_OK;
+}
+
+size_t sht_order_workspace_bytes(sht_plan_t plan, int R) {
+  if (!plan || !plan->maps || R < 1) return 0;
+  return 2 * align256(static_cast<size_t>(plan->rows_v) * R * 8);
+}
+
+int sht_order_apply(sht_plan_t plan, const double* in, double* out, int R, int transpose, void* ws, size_t wsb,
+                    void* stream) {
+  sht_plan_s* P = plan;
+  if (!P || !P->maps || !in || !out || !ws || R < 1 || R > 65535 || (transpose != 0 && transpose != 1))
+    return SHT_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % 16 || reinterpret_cast<uintptr_t>(out) % 16 ||
+      reinterpret_cast<uintptr_t>(ws) % 256)
+    return SHT_EINVAL;
+  if (wsb < sht_order_workspace_bytes(plan, R)) return SHT_EINVAL;
+  const size_t bytes = static_cast<size_t>(P->rows_in) * R * 8;
+  const char *a = reinterpret_cast<const char*>(in), *b = reinterpret_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return SHT_EINVAL;  // in and out overlap
+  DeviceScope ds(P->device);
+  if (!ds.ok()) return SHT_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* v0 = static_cast<double*>(ws);
+  double* v1 = reinterpret_cast<double*>(static_cast<char*>(ws) + align256(static_cast<size_t>(P->rows_v) * R * 8));
+  const bool prof = P->prof.on;
+  const std::string fs = prof ? "/R" + std::to_string(R) + "/fp64" : std::string();
+  const Work fw{2.0 * P->final_fac * R, 8.0 * (P->final_fac + (P->final_rows_v + P->final_rows_y) * R)};
+  double* xin = const_cast<double*>(in);
+  if (!transpose) {
+    if (P->step_cnt[0] > 0)
+      STAGE("order.level0" + fs, level_work(P, 0, R),
+            launch_level(P, 0, false, in, v0, R, SHT_FP64, s, nullptr, -1, xin));
+    for (int t = 1; t <= P->Lmax; ++t)
+      STAGE("order.level" + std::to_string(t) + fs, level_work(P, t, R),
+            launch_level(P, t, false, (t - 1) % 2 ? v1 : v0, t % 2 ? v1 : v0, R, SHT_FP64, s, nullptr, -1, xin));
+    STAGE("order.final" + fs, fw, launch_order_final(P, false, v0, v1, nullptr, nullptr, out, nullptr, R, s));
+  } else {
+    STAGE("order_t.final" + fs, fw, launch_order_final(P, true, nullptr, nullptr, v0, v1, nullptr, in, R, s));
+    for (int t = P->Lmax; t >= 1; --t)
+      STAGE("order_t.level" + std::to_string(t) + fs, level_work(P, t, R),
+            launch_level(P, t, true, t % 2 ? v1 : v0, (t - 1) % 2 ? v1 : v0, R, SHT_FP64, s, nullptr, -1, out));
+    if (P->step_cnt[0] > 0)
+      STAGE("order_t.level0" + fs, level_work(P, 0, R),
+            launch_level(P, 0, true, v0, out, R, SHT_FP64, s, nullptr, -1, out));
+  }
+  return SHT_OK;
+}
+
 int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
   if (!plan) return SHT_EINVAL;
   if (precision < SHT_FP64 || precision > SHT_INT8) return SHT_EINVAL;
+  if (plan->maps && precision != SHT_FP64) return SHT_EUNSUPPORTED;
   if (precision == SHT_FP64) return plan->d.fac ? SHT_OK : SHT_ENOTREADY;
   DeviceScope ds(plan->device);
   if (!ds.ok()) return SHT_EHIP;
@@ -414,7 +497,7 @@ void sht_destroy(sht_plan_t plan) {
 }
 
 size_t sht_workspace_bytes(sht_plan_t plan, int nfields, int precision) {
-  if (!plan || nfields < 1 || precision < SHT_FP64 || precision > SHT_INT8) return 0;
+  if (!plan || plan->maps || nfields < 1 || precision < SHT_FP64 || precision > SHT_INT8) return 0;
   return ws_bytes(plan, nfields);
 }
 
@@ -518,7 +601,7 @@ int sht_plan_tree(sht_plan_t plan, int m, int p, int* levels, int* n_cols) {
 }
 
 int sht_plan_columns(sht_plan_t plan, int m, int p, double* q, int ldq) {
-  if (!plan || !q || m < 0 || m >= 2 * plan->l || (p != 0 && p != 1) || ldq < plan->l)
+  if (!plan || plan->maps || !q || m < 0 || m >= 2 * plan->l || (p != 0 && p != 1) || ldq < plan->l)
     return SHT_EINVAL;
   DeviceScope ds(plan->device);
   if (!ds.ok()) return SHT_EHIP;
@@ -573,7 +656,7 @@ int sht_plan_columns(sht_plan_t plan, int m, int p, double* q, int ldq) {
 }
 
 int sht_dense_q(sht_plan_t plan, int mp0, int count, double* q, long long stride, void* stream) {
-  if (!plan || !q || count < 1 || mp0 < 0 || mp0 + count > 4 * plan->l ||
+  if (!plan || plan->maps || !q || count < 1 || mp0 < 0 || mp0 + count > 4 * plan->l ||
       stride < static_cast<long long>(plan->l) * plan->l)
     return SHT_EINVAL;
   DeviceScope ds(plan->device);

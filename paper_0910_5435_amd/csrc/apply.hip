@@ -273,6 +273,54 @@ k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
   }
 }
 
+// ------------------------------------------------------------------------- order maps
+// Final of a per-order map A^{(m,p)} (Section 4): y = S w on the task's own output rows, with
+// neither the parity unfold nor a row scaling (A carries the square roots of its weights).
+template <int RT>
+__global__ void __launch_bounds__(kThreads)
+k_order_final_synth(const OrderFinal* __restrict__ tasks, const double* __restrict__ fac,
+                    const double* __restrict__ v0buf, const double* __restrict__ v1buf,
+                    double* __restrict__ y, int R) {
+  extern __shared__ double lds[];
+  const OrderFinal ft = tasks[blockIdx.x];
+  const int r0 = blockIdx.y * RT;
+  const double* V = ft.vbuf ? v1buf : v0buf;
+  const int k = ft.k, h = ft.h;
+  for (int e = threadIdx.x; e < k * RT; e += kThreads)
+    lds[e] = V[(static_cast<long long>(ft.in_row) + e / RT) * R + r0 + e % RT];
+  __syncthreads();
+  const double* S = fac + ft.fac;  // h x k, column-major
+  for (int e = threadIdx.x; e < h * RT; e += kThreads) {
+    const int i = e / RT, c = e % RT;
+    double acc = 0.0;
+    for (int a = 0; a < k; ++a) acc = fma(S[static_cast<long long>(a) * h + i], lds[a * RT + c], acc);
+    y[(static_cast<long long>(ft.out_row) + i) * R + r0 + c] = acc;
+  }
+}
+
+// Transposed: w = S^T y, from the transposed pool (S^T is k x h column-major there).
+template <int RT>
+__global__ void __launch_bounds__(kThreads)
+k_order_final_trans(const OrderFinal* __restrict__ tasks, const double* __restrict__ fac_t,
+                    const double* __restrict__ yin, double* __restrict__ v0buf,
+                    double* __restrict__ v1buf, int R) {
+  extern __shared__ double lds[];
+  const OrderFinal ft = tasks[blockIdx.x];
+  const int r0 = blockIdx.y * RT;
+  double* V = ft.vbuf ? v1buf : v0buf;
+  const int k = ft.k, h = ft.h;
+  for (int e = threadIdx.x; e < h * RT; e += kThreads)
+    lds[e] = yin[(static_cast<long long>(ft.out_row) + e / RT) * R + r0 + e % RT];
+  __syncthreads();
+  const double* St = fac_t + ft.fac;
+  for (int e = threadIdx.x; e < k * RT; e += kThreads) {
+    const int a = e / RT, c = e % RT;
+    double acc = 0.0;
+    for (int i = 0; i < h; ++i) acc = fma(St[static_cast<long long>(i) * k + a], lds[i * RT + c], acc);
+    V[(static_cast<long long>(ft.in_row) + a) * R + r0 + c] = acc;
+  }
+}
+
 // Largest column tile (<= 16) that divides R and keeps the LDS footprint of
 // `per_col` doubles per column within 64 KiB.
 int pick_rt(int R, long long per_col) {
@@ -361,6 +409,34 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
     default: LAUNCH_FINAL(1); break;
   }
 #undef LAUNCH_FINAL
+  return hipGetLastError();
+}
+
+hipError_t launch_order_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
+                              double* v0w, double* v1w, double* y, const double* yin, int R, hipStream_t s) {
+  if (P->n_ofinal == 0) return hipSuccess;
+  const long long rows = std::max(1, transpose ? P->ofinal_maxh : P->ofinal_maxk);
+  const int RT = pick_rt(R, rows);
+  if (rows * RT * 8 > 65536 || R / RT > 65535) return hipErrorInvalidConfiguration;
+  dim3 grid(static_cast<unsigned>(P->n_ofinal), R / RT);
+  const size_t lds = sizeof(double) * RT * rows;
+#define LAUNCH_OFINAL(RTV)                                                                           \
+  do {                                                                                                \
+    if (transpose)                                                                                    \
+      hipLaunchKernelGGL(k_order_final_trans<RTV>, grid, dim3(kThreads), lds, s, P->d.ofinals,        \
+                         P->d.fac_t, yin, v0w, v1w, R);                                               \
+    else                                                                                              \
+      hipLaunchKernelGGL(k_order_final_synth<RTV>, grid, dim3(kThreads), lds, s, P->d.ofinals,        \
+                         P->d.fac, v0, v1, y, R);                                                     \
+  } while (0)
+  switch (RT) {
+    case 16: LAUNCH_OFINAL(16); break;
+    case 8: LAUNCH_OFINAL(8); break;
+    case 4: LAUNCH_OFINAL(4); break;
+    case 2: LAUNCH_OFINAL(2); break;
+    default: LAUNCH_OFINAL(1); break;
+  }
+#undef LAUNCH_OFINAL
   return hipGetLastError();
 }
 

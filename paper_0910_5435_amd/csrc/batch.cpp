@@ -355,7 +355,7 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
   int device = -1;
   for (int r = 0; r < nreq; ++r) {
     const sht_request& q = reqs[r];
-    if (!q.plan || q.nfields < 1 || !q.input || !q.output) return SHT_EINVAL;
+    if (!q.plan || q.plan->maps || q.nfields < 1 || !q.input || !q.output) return SHT_EINVAL;
     if (reinterpret_cast<uintptr_t>(q.input) % 16 || reinterpret_cast<uintptr_t>(q.output) % 16)
       return SHT_EINVAL;
     if (device < 0) device = q.plan->device;

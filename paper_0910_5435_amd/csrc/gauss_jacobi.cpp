@@ -149,8 +149,12 @@ bool bad_args(int m, int n, int parity) {
 }
 
 template <typename F>
-void split_range(int n, F&& fn) {
-  const int nt = std::min(sht::host_thread_count(), std::max(1, n / 64));
+void split_range(int n, F&& fn, bool threads = true) {
+  const int nt = threads ? std::min(sht::host_thread_count(), std::max(1, n / 64)) : 1;
+  if (nt == 1) {
+    fn(0, n);
+    return;
+  }
   std::vector<std::thread> th;
   for (int k = 0; k < nt; ++k)
     th.emplace_back(fn, static_cast<int>(static_cast<long long>(n) * k / nt),
@@ -159,7 +163,7 @@ void split_range(int n, F&& fn) {
 }
 
 // Nodes x_0 < ... < x_{n-1} in (0, 1), with log |R_L'| at each.
-void nodes(int m, int n, int p, std::vector<double>& x, std::vector<double>& log_deriv) {
+void nodes(int m, int n, int p, std::vector<double>& x, std::vector<double>& log_deriv, bool threads = true) {
   const Jacobi J(m, n, p);
   const StepOne S(m, m + p + 2 * n);
   x.assign(n, 0.0);
@@ -190,10 +194,29 @@ void nodes(int m, int n, int p, std::vector<double>& x, std::vector<double>& log
       x[i] = xi;
       log_deriv[i] = ld;
     }
-  });
+  }, threads);
 }
 
 }  // namespace
+
+namespace sht {
+
+int gj_matrix(int m, int n, int parity, double* a, int lda, bool threads) {
+  if (bad_args(m, n, parity) || !a || lda < n) return SHT_EINVAL;
+  std::vector<double> xs, ld;
+  nodes(m, n, parity, xs, ld, threads);
+  const StepOne S(m, m + parity + 2 * n);
+  split_range(n, [&](int i0, int i1) {
+    std::vector<double> q(n);
+    for (int i = i0; i < i1; ++i) {
+      const double inv = 1.0 / std::sqrt(S.row(xs[i], parity, n, q.data()));
+      for (int j = 0; j < n; ++j) a[i + static_cast<long long>(j) * lda] = q[j] * inv;
+    }
+  }, threads);
+  return SHT_OK;
+}
+
+}  // namespace sht
 
 extern "C" {
 
@@ -213,18 +236,7 @@ int sht_gj_rule(int m, int n, int parity, double* x, double* w) {
 }
 
 int sht_gj_matrix(int m, int n, int parity, double* a, int lda) {
-  if (bad_args(m, n, parity) || !a || lda < n) return SHT_EINVAL;
-  std::vector<double> xs, ld;
-  nodes(m, n, parity, xs, ld);
-  const StepOne S(m, m + parity + 2 * n);
-  split_range(n, [&](int i0, int i1) {
-    std::vector<double> q(n);
-    for (int i = i0; i < i1; ++i) {
-      const double inv = 1.0 / std::sqrt(S.row(xs[i], parity, n, q.data()));
-      for (int j = 0; j < n; ++j) a[i + static_cast<long long>(j) * lda] = q[j] * inv;
-    }
-  });
-  return SHT_OK;
+  return sht::gj_matrix(m, n, parity, a, lda, true);
 }
 
 }  // extern "C"

@@ -118,4 +118,8 @@ class BfTree {
 
 int butterfly_depth(int cols, int C);
 
+// The n x n matrix of (transform) / (transform2) for order m and parity p (gauss_jacobi.cpp),
+// column-major with leading dimension lda; threads = false computes it on the calling thread.
+int gj_matrix(int m, int n, int p, double* a, int lda, bool threads);
+
 }  // namespace sht

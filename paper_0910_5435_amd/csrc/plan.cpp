@@ -162,6 +162,10 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   std::vector<PairShape> shapes(npairs);
   for (int mp = 0; mp < npairs; ++mp) {
     shapes[mp] = pair_shape(l, C, mp);
+    if (P->maps) {  // A^{(m,p)} is n_p x n_p, each pair with its own depth (its finals are its own)
+      shapes[mp].rows = shapes[mp].cols;
+      shapes[mp].L = butterfly_depth(shapes[mp].cols, C);
+    }
     P->n_cols[mp] = shapes[mp].cols;
     P->levels[mp] = shapes[mp].L;
     Lmax = std::max(Lmax, shapes[mp].L);
@@ -184,11 +188,48 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
       if (rc != SHT_OK) return rc;
     }
   }
-  for (int mp = nvalid; mp < npairs; ++mp)
+  const int nthreads = o.host_threads > 0 ? o.host_threads : host_thread_count();
+  double t_cols = 0.0, t_comp = 0.0;
+  int err = SHT_OK;
+  if (P->maps) {
+    // Per-order maps (Section 4): every A^{(m,p)} on the host (its nodes by Sturm bisection
+    // and Newton, its rows by the normalized recurrence), one pair per thread, largest first;
+    // the leaves then go to the depth-first construction in column order, as for Q^{(m,p)}.
+    std::atomic<int> bad{0};
+    std::vector<double> tc(npairs, 0.0), ti(npairs, 0.0);
+    parallel_for(npairs, nthreads, [&](int mp) {
+      if (bad) return;
+      try {
+        const int n = P->n_cols[mp];
+        const double ta = now_s();
+        std::vector<double> a(std::max<size_t>(1, static_cast<size_t>(n) * n));
+        if (n > 0 && gj_matrix(mp / 2, n, mp % 2, a.data(), n, false) != SHT_OK) {
+          bad = SHT_EINTERNAL;
+          return;
+        }
+        const double tb = now_s();
+        BfTree& tr = trees[mp];
+        tr.init(n, n, C, P->levels[mp], P->eps);
+        for (int c = 0; c < (1 << tr.L()); ++c)
+          tr.add_leaf(c, a.data() + static_cast<size_t>(std::min(c * C, n)) * n, std::max(n, 1));
+        tc[mp] = tb - ta;
+        ti[mp] = now_s() - tb;
+      } catch (const std::bad_alloc&) {
+        bad = SHT_ENOMEM;
+      } catch (...) {
+        bad = SHT_EINTERNAL;
+      }
+    });
+    if (bad) return bad;
+    for (int mp = 0; mp < npairs; ++mp) {  // thread time, per thread
+      t_cols += tc[mp] / std::min(nthreads, npairs);
+      t_comp += ti[mp] / std::min(nthreads, npairs);
+    }
+  }
+  for (int mp = nvalid; mp < npairs && !P->maps; ++mp)
     trees[mp].init(l, P->n_cols[mp], C, P->levels[mp], P->eps);
 
   // Device-side column generation, batch by batch.
-  const int nthreads = o.host_threads > 0 ? o.host_threads : host_thread_count();
   const size_t chunk_doubles = static_cast<size_t>(C) * l;
   int batch = static_cast<int>(std::max<size_t>(2, (size_t(64) << 20) / (chunk_doubles * 8)));
   batch = std::min(batch, npairs);
@@ -213,9 +254,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   std::unique_ptr<double, void (*)(double*)> host_guard(host_chunk,
                                                           [](double* q) { (void)hipHostFree(q); });
 
-  double t_cols = 0.0, t_comp = 0.0;
-  int err = SHT_OK;
-  for (int b0 = 0; b0 < npairs && err == SHT_OK; b0 += batch) {
+  for (int b0 = 0; b0 < npairs && err == SHT_OK && !P->maps; b0 += batch) {
     const int nb = std::min(batch, npairs - b0);
     if (b0 + nb <= nvalid) continue;  // every butterfly of the batch came from the cache
     std::vector<int> hm(nb), hp(nb), hn(nb);
@@ -349,7 +388,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (in_rows > INT32_MAX || v_rows > INT32_MAX) return SHT_EUNSUPPORTED;
   P->rows_in = in_rows;
   P->rows_v = v_rows;
-  P->rows_y = static_cast<long long>(L2) * L2;
+  P->rows_y = P->maps ? in_rows : static_cast<long long>(L2) * L2;
 
   // Every T and final S of the trees is packed exactly once (empty ones add nothing), so
   // the pool's size is known before packing starts.
@@ -415,7 +454,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   // leaves directly (in column order) with their index lists renumbered through the
   // leaves' skeleton orders, and the leaf step is dropped for that order.
   std::vector<char> fold(npairs, 0);
-  for (int mp = 0; mp < npairs; ++mp) {
+  for (int mp = 0; mp < npairs && !P->maps; ++mp) {  // the order maps read their own input rows
     const BfTree& T = trees[mp];
     if (T.L() < 1) continue;
     bool ident = true;
@@ -524,7 +563,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     const BfFinal* f[2];
   };
   std::vector<FProto> fprotos;
-  for (int m = 0; m < L2; ++m) {
+  for (int m = 0; m < L2 && !P->maps; ++m) {
     const BfTree& T0 = trees[2 * m];
     const BfTree& T1 = trees[2 * m + 1];
     const int L = T0.L();
@@ -575,6 +614,34 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
     P->final_maxh = std::max(P->final_maxh, ft.h);
     P->final_maxk = std::max(P->final_maxk, kmx);
   }
+  // Per-order maps: one final per (pair, row node), written straight to its output rows.
+  std::vector<OrderFinal> ofinals;
+  for (int mp = 0; mp < npairs && P->maps; ++mp) {
+    const BfTree& T = trees[mp];
+    const int L = T.L();
+    for (int r = 0; r < (1 << L); ++r) {
+      const BfFinal& f = T.final_block(r);
+      if (f.h <= 0) continue;
+      OrderFinal of{};
+      of.in_row = P->v_base[mp] + voff[mp][L][r];
+      of.out_row = P->in_base[mp] + f.row0;
+      of.h = f.h;
+      of.k = f.k;
+      of.vbuf = L % 2;
+      of.fac = static_cast<int64_t>(fac.size());
+      fac.append(f.S.data(), f.S.size());
+      I8Off unused;
+      if (!f.S.empty()) fblocks.push_back({of.fac, f.h, f.k});
+      i8_place(of.fac, f.S.empty() ? 0 : f.h, f.k, unused);
+      ofinals.push_back(of);
+      P->final_fac += static_cast<double>(f.h) * f.k;
+      P->final_rows_v += f.k;
+      P->final_rows_y += f.h;
+      P->ofinal_maxk = std::max(P->ofinal_maxk, f.k);
+      P->ofinal_maxh = std::max(P->ofinal_maxh, f.h);
+    }
+  }
+  P->n_ofinal = static_cast<long long>(ofinals.size());
   P->n_final = static_cast<long long>(finals.size());
   P->n_fac = static_cast<long long>(fac.size());
   P->n_dig = dig_off;
@@ -618,6 +685,8 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.idx), idx.data(), idx.size() * sizeof(uint16_t));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.tasks), tasks.data(), tasks.size() * sizeof(LevelTask));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.finals), finals.data(), finals.size() * sizeof(FinalTask));
+  if (e == hipSuccess)
+    e = up(reinterpret_cast<void**>(&P->d.ofinals), ofinals.data(), ofinals.size() * sizeof(OrderFinal));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.pairs), pd.data(), pd.size() * sizeof(PairDesc));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.invD), invD.data(), invD.size() * sizeof(double));
   if (e == hipSuccess) e = up(reinterpret_cast<void**>(&P->d.D), D.data(), D.size() * sizeof(double));
@@ -637,15 +706,17 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   P->stats.device_bytes =
       static_cast<long long>(2 * n_fac_total * 8 + idx.size() * 2 + tasks.size() * sizeof(LevelTask) +
-                             finals.size() * sizeof(FinalTask) + pd.size() * sizeof(PairDesc) +
+                             finals.size() * sizeof(FinalTask) + ofinals.size() * sizeof(OrderFinal) +
+                             pd.size() * sizeof(PairDesc) +
                              (invD.size() + D.size() + tw.size()) * 8);
   return SHT_OK;
 }
 
 void free_plan_device(sht_plan_s* P) {
-  void* ptrs[] = {P->d.fac,    P->d.fac_t,    P->d.fac_hl, P->d.fac_t_hl, P->d.dig,
-                  P->d.dex,    P->d.i8blocks, P->d.blocks, P->d.idx,      P->d.tasks,
-                  P->d.finals, P->d.pairs,    P->d.invD,   P->d.D,        P->d.twiddle};
+  void* ptrs[] = {P->d.fac,    P->d.fac_t,   P->d.fac_hl, P->d.fac_t_hl, P->d.dig,
+                  P->d.dex,    P->d.i8blocks, P->d.blocks, P->d.idx,     P->d.tasks,
+                  P->d.finals, P->d.ofinals, P->d.pairs,  P->d.invD,     P->d.D,
+                  P->d.twiddle};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   P->d = DeviceFactors{};

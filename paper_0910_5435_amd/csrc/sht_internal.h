@@ -68,6 +68,19 @@ struct FinalTask {
   I8Off i8[2];        // the same S in the int8-slice pools
 };
 
+// Final skeleton product of one per-order map (Section 4: the n x n matrix A^{(m,p)} of
+// (transform) / (transform2) on its own nodes) and one row node r at level L: y = S w on
+// rows [out_row, out_row + h) of the output, no parity unfold and no row scaling (the
+// square roots of the weights are inside A).
+struct OrderFinal {
+  int32_t in_row;     // V rows of the level-L block
+  int32_t out_row;    // first output row (pair base + row0)
+  int32_t h, k;       // rows, rank
+  int32_t vbuf;       // which V buffer holds the block (L % 2)
+  int32_t pad;
+  int64_t fac;        // S (h x k, column-major) offset; the transposed pool holds S^T there
+};
+
 // Layout descriptor of one (m, p) pair in the internal coefficient buffer.
 struct PairDesc {
   int32_t m, p, n;    // order, parity, number of columns n_p
@@ -110,6 +123,7 @@ struct DeviceFactors {
   uint16_t* idx = nullptr;     // skel/red index lists
   LevelTask* tasks = nullptr;  // all level tasks, step by step
   FinalTask* finals = nullptr;
+  OrderFinal* ofinals = nullptr;  // per-order map plans: final skeletons, one per (pair, row node)
   PairDesc* pairs = nullptr;
   double* invD = nullptr;      // 1 / sqrt(2 w_i) on the positive nodes
   double* D = nullptr;         // sqrt(2 w_i)
@@ -221,6 +235,7 @@ struct sht_plan_s {
   int device = 0;
   int precision = SHT_FP64;
   int kind = SHT_COMPLEX;
+  bool maps = false;  // a plan of the per-order maps of Section 4 (sht_order_plan), not of the SHT
   double eps = 0.0;
   std::vector<double> xp, wp;           // positive nodes ascending and their weights
   std::vector<int> n_cols, levels;      // per pair mp = 2m + p
@@ -238,6 +253,8 @@ struct sht_plan_s {
   double final_fac = 0, final_rows_v = 0, final_rows_y = 0;
   sht::Profiler prof;
   long long n_final = 0;
+  long long n_ofinal = 0;        // per-order map plans: OrderFinal count, largest rank and rows
+  int ofinal_maxk = 0, ofinal_maxh = 0;
   long long n_pairs = 0;
   long long n_folded = 0;  // orders whose leaf step is folded into level 1
   sht::DeviceFactors d;
@@ -261,6 +278,9 @@ hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const dou
 hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                         double* v0w, double* v1w, double* y, const double* yin, int R,
                         int precision, bool adjoint, hipStream_t s, int cls = -1);
+// Per-order map plans (FP64): y rows = S w from V (synthesis direction), or V = S^T y rows.
+hipError_t launch_order_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
+                              double* v0w, double* v1w, double* y, const double* yin, int R, hipStream_t s);
 // fptr (may be null): one grid base pointer per field instead of a contiguous array.
 hipError_t launch_fft_synth(const sht_plan_s* P, const double* y, double* grid, int F, int R,
                             hipStream_t s, double* const* fptr = nullptr);

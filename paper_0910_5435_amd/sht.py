@@ -264,6 +264,87 @@ def _align(ptr):
     return (ptr + 255) & ~255
 
 
+class OrderPlan:
+    """The per-order maps of Section 4 on the GPU (sht_order_plan): for every order m < 2l and
+    parity p, the orthogonal n_p x n_p matrix A^{(m,p)} of (transform) / (transform2) on its own
+    Gauss-Jacobi-type nodes, butterfly-compressed.  Vectors live in "pair rows": an
+    (rows, R) float64 device array in which pair 2m + p owns rows [row0, row0 + n_p)."""
+
+    def __init__(self, l, eps=1e-13, leaf_width=64, host_threads=0, device=None):
+        lib = L.load()
+        opts = L.PlanOpts()
+        lib.sht_default_opts(ctypes.byref(opts))
+        opts.leaf_width = int(leaf_width)
+        opts.host_threads = int(host_threads)
+        opts.device = -1 if device is None else int(device)
+        handle = ctypes.c_void_p()
+        L.check(lib.sht_order_plan(int(l), float(eps), ctypes.byref(opts), ctypes.byref(handle)),
+                "sht_order_plan")
+        self._h = handle
+        self.l = int(l)
+        self.eps = float(eps)
+        self.leaf_width = int(leaf_width)
+        self.rows = int(lib.sht_order_rows(handle))
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.load().sht_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self):
+        st = L.Stats()
+        L.check(L.load().sht_plan_stats(self._h, ctypes.byref(st)), "sht_plan_stats")
+        return {name: getattr(st, name) for name, _ in L.Stats._fields_}
+
+    def layout(self, m, p):
+        """(row0, n_p) of pair (m, p)."""
+        r0, n = ctypes.c_longlong(), ctypes.c_int()
+        L.check(L.load().sht_order_layout(self._h, int(m), int(p), ctypes.byref(r0), ctypes.byref(n)),
+                "sht_order_layout")
+        return r0.value, n.value
+
+    def profile(self, enable=True):
+        L.check(L.load().sht_profile_enable(self._h, 1 if enable else 0), "sht_profile_enable")
+
+    profile_reset = Plan.profile_reset
+    profile_read = Plan.profile_read
+
+    def apply(self, x, out=None, transpose=False, stream=None):
+        """out = A x (coefficients -> node values) for every pair, or A^T x with transpose=True
+        (the inverse).  x: float64 (rows, R) or (rows,) on the device, contiguous."""
+        torch = _torch()
+        squeeze = x.dim() == 1
+        if squeeze:
+            x = x.unsqueeze(1)
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != torch.float64 or x.shape[0] != self.rows:
+            raise ValueError(f"x must be a contiguous float64 device tensor with {self.rows} rows")
+        R = x.shape[1]
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.shape != x.shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor shaped like x")
+        nb = int(L.load().sht_order_workspace_bytes(self._h, int(R)))
+        if self._ws is None or self._ws.numel() < nb + 256 or self._ws.device != x.device:
+            self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=x.device)
+        _used_on(stream, self._ws, out)
+        L.check(L.load().sht_order_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         int(R), 1 if transpose else 0, ctypes.c_void_p(_align(self._ws.data_ptr())),
+                                         self._ws.numel() - 256, _stream_handle(stream)), "sht_order_apply")
+        return out[:, 0] if squeeze else out
+
+
 BATCH_OPS = {"synth": L.SHT_BATCH_SYNTH, "analyze": L.SHT_BATCH_ANALYZE, "adjoint": L.SHT_BATCH_ADJOINT}
 
 

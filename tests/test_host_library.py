@@ -340,3 +340,27 @@ def test_argument_validation_without_gpu():
         assert lib.sht_bf_build(a.ctypes.data_as(L._DP), 4, 4, 4, 1, levels, 1e-13, ctypes.byref(bfh)) == L.SHT_EINVAL
     assert lib.sht_strerror(L.SHT_EHIP) == b"HIP runtime error"
     assert lib.sht_version()
+
+
+def test_order_plan_argument_validation_without_gpu():
+    # sht_order_plan validates its options before it touches the device
+    lib = L.load()
+    h = ctypes.c_void_p()
+    opts = L.PlanOpts()
+    lib.sht_default_opts(ctypes.byref(opts))
+    assert lib.sht_order_plan(0, 1e-13, None, ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_order_plan(8, 0.0, None, ctypes.byref(h)) == L.SHT_EINVAL
+    assert lib.sht_order_plan(8, 1e-13, None, None) == L.SHT_EINVAL
+    assert lib.sht_order_plan(4096, 1e-13, None, ctypes.byref(h)) == L.SHT_EUNSUPPORTED
+    opts.leaf_width = 1  # a leaf of one column cannot have fewer row blocks than rows
+    assert lib.sht_order_plan(8, 1e-13, ctypes.byref(opts), ctypes.byref(h)) == L.SHT_EINVAL
+    opts.leaf_width = 8
+    opts.precision = L.SHT_SPLIT32
+    assert lib.sht_order_plan(8, 1e-13, ctypes.byref(opts), ctypes.byref(h)) == L.SHT_EUNSUPPORTED
+    opts.precision = L.SHT_FP64
+    opts.cache_dir = b"/tmp"
+    assert lib.sht_order_plan(8, 1e-13, ctypes.byref(opts), ctypes.byref(h)) == L.SHT_EUNSUPPORTED
+    assert lib.sht_order_rows(None) == L.SHT_EINVAL
+    assert lib.sht_order_layout(None, 0, 0, None, None) == L.SHT_EINVAL
+    assert lib.sht_order_workspace_bytes(None, 4) == 0
+    assert lib.sht_order_apply(None, None, None, 1, 0, None, 0, None) == L.SHT_EINVAL
