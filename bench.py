@@ -49,10 +49,13 @@ def parse():
     ap.add_argument("--power", type=float, default=1.5)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle check of whole fields (and with it the CPU baseline and the gate)")
-    ap.add_argument("--workload", default="metric", choices=["metric", "mixed", "single"],
+    ap.add_argument("--workload", default="metric", choices=["metric", "mixed", "single", "orders"],
                     help="metric: the l=1024, 64-field line; mixed: 96 requests of mixed bandlimits "
                          "through the batched persistent launch, beside one call per request; single: "
-                         "one complex field at l=256 in FP64 (the factor-streaming regime)")
+                         "one complex field at l=256 in FP64 (the factor-streaming regime); orders: the "
+                         "per-order maps of Section 4 for every order of bandlimit --l on "
+                         "--order-columns columns, forward then inverse")
+    ap.add_argument("--order-columns", type=int, default=4, help="R of the orders workload")
     ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
                     help="bandlimits of the mixed workload (uniform draw); the full set 64..2048 needs "
                          "about 210 GB for its inputs and outputs alone")
@@ -313,7 +316,7 @@ def grid_bytes(l, F):
     return float(F) * 2 * l * 4 * l * 16
 
 
-def roofline(prof, precision, l, F):
+def roofline(prof, precision, l, F, R=None):
     """The single kernel launch with the largest share of the timed kernel time.
 
     A Legendre launch (levels, finals) at many fields is a dense contraction, bound by the
@@ -326,7 +329,14 @@ def roofline(prof, precision, l, F):
     name, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     mean_s = rec["ms"] / rec["launches"] / 1e3
     peak_f = unit_peak(precision)
-    if ".fft/" not in name:
+    R = 4 * F if R is None else R
+    if ".fft/" not in name and 2.0 * R / 8.0 < peak_f / PEAK["hbm"]:
+        # 2R flops per 8-byte factor word below the ridge point: the launch streams its factors
+        roof = {"bound": "hbm", "achieved": rec["bytes"] / mean_s / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": rec["bytes"] / mean_s / PEAK["hbm"], "bytes_per_launch": rec["bytes"],
+                "flops_per_launch": rec["flops"],
+                "note": "algorithmic bytes: factor words plus the vector rows the launch reads and writes"}
+    elif ".fft/" not in name:
         roof = {"bound": "mfma", "achieved": rec["flops"] / mean_s / 1e12, "peak": peak_f / 1e12,
                 "unit": "TFLOP/s", "frac": rec["flops"] / mean_s / peak_f,
                 "flops_per_launch": rec["flops"],
@@ -447,6 +457,91 @@ def mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def orders(args):
+    """The per-order maps of Section 4 (sht_order_apply): for every order m < 2l and parity p the
+    n_p x n_p orthogonal matrix of (transform) / (transform2) on its own nodes, butterfly-
+    compressed, applied to R columns; one step = the forward map of every pair then the inverse
+    (the transposed butterfly).  The oracle applies its dense matrices to the same vectors on a
+    few pairs (timed: the CPU baseline) and both directions are checked against it there."""
+    import numpy as np
+    import torch
+
+    from oracle import gauss_jacobi as gj
+    from paper_0910_5435_amd import OrderPlan
+
+    l, R = args.l, args.order_columns
+    t0 = time.perf_counter()
+    plan = OrderPlan(l, eps=args.eps, leaf_width=args.leaf_width)
+    t_plan = time.perf_counter() - t0
+    st = plan.stats()
+    print(f"# order maps l={l}: plan {t_plan:.1f} s, k_max {st['k_max']}, k_avg {st['k_avg']:.1f}, "
+          f"factors {st['factor_entries']:.3e}", file=sys.stderr, flush=True)
+    x_np = np.random.default_rng(0).standard_normal((plan.rows, R))
+    x = torch.from_numpy(x_np).to("cuda")
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+
+    def step():
+        plan.apply(x, out=y)
+        plan.apply(y, out=z, transpose=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for i in range(args.steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    ms = float(np.median(per))
+    plan.profile_reset()
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(False)
+    prof = plan.profile_read()
+    rt = float(torch.linalg.norm(z - x) / torch.linalg.norm(x))
+    y_np = y.cpu().numpy()
+    z_np = z.cpu().numpy()
+    sample = [(m, p) for m in sorted({0, l // 2, l, 2 * l - 2}) for p in (0, 1)]
+    errs, t_or = [], 0.0
+    for m, p in sample:
+        r0, n = plan.layout(m, p)
+        ta = time.perf_counter()
+        A = gj.matrix(m, n, p)
+        ref = A @ x_np[r0:r0 + n]
+        t_or += time.perf_counter() - ta
+        errs.append(max(float(np.linalg.norm(y_np[r0:r0 + n] - ref) / np.linalg.norm(ref)),
+                        float(np.linalg.norm(z_np[r0:r0 + n] - A.T @ y_np[r0:r0 + n]) /
+                              np.linalg.norm(y_np[r0:r0 + n]))))
+    rows_s = sum(plan.layout(m, p)[1] for m, p in sample)
+    out = {"metric": f"per-order map pairs/s (every order of l={l}, forward + inverse, {R} columns)",
+           "value": 1e3 / ms, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"per-order maps (transform)/(transform2), every (m, p) of l={l}, {R} "
+                                  f"N(0,1) columns", "l": l, "columns": R, "leaf_width": args.leaf_width,
+                      "eps": args.eps},
+           "roofline": roofline(prof, "fp64", l, 1, R=R),
+           "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in sorted(prof.items())},
+           "round_trip_rel_err": rt,
+           "oracle_check": {"pairs": sample, "rel_l2_max": max(errs)},
+           "cpu_baseline": {"value": rows_s / plan.rows / t_or, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                            "sample": f"dense oracle matrices of {len(sample)} pairs ({rows_s} of {plan.rows} "
+                                      f"rows), built and applied in {t_or:.1f} s, scaled by rows"},
+           "t_plan_s": t_plan,
+           "plan": {k: st[k] for k in ("k_max", "k_avg", "k_sd", "factor_entries", "dense_entries",
+                                       "t_columns_s", "t_compress_s")}}
+    print(f"# order maps: {out['value']:.1f} pairs/s ({ms:.3f} ms), round trip {rt:.2e}, oracle {max(errs):.2e}",
+          file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    if max(errs) > 1e-11 or rt > 1e-11:
+        sys.exit(1)
+
+
 GATE = 1e-9  # relative l2 per field and direction against the oracle (split-FP32)
 
 
@@ -458,6 +553,8 @@ def main():
         sys.exit(2)
     if args.workload == "mixed":
         return mixed(args)
+    if args.workload == "orders":
+        return orders(args)
     metric = METRIC
     if args.workload == "single":
         # one complex field, l = 256, FP64 butterfly (vector kernels at R = 4)

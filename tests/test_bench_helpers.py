@@ -73,6 +73,18 @@ def test_roofline_picks_the_largest_launch_and_its_bound():
     assert abs(r["achieved"] - gb / 0.02 / 1e9) < 1e-6 and r["nonalgorithmic_bytes_per_launch"] == 8e9 - gb
 
 
+def test_roofline_of_a_factor_streaming_launch_is_hbm_bound():
+    # one complex field (R = 4): 2 x 4 flops per 8-byte factor word, below the FP64 ridge point
+    # (78.6 TFLOP/s over 8 TB/s): bound by HBM on the launch's algorithmic bytes
+    prof = {"analysis.final/F1/fp64": {"ms": 2.0, "launches": 10, "flops": 1e8, "bytes": 1.2e8},
+            "synth.level1/F1/fp64": {"ms": 1.0, "launches": 10, "flops": 1e8, "bytes": 1.1e8}}
+    r = bench.roofline(prof, precision="fp64", l=256, F=1)
+    assert r["kernel"] == "analysis.final/F1/fp64" and r["bound"] == "hbm" and r["peak"] == 8000.0
+    assert abs(r["achieved"] - 1.2e8 / 2e-4 / 1e9) < 1e-9 and abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15
+    # the same launch at 64 columns per factor word is a contraction again
+    assert bench.roofline(prof, precision="fp64", l=256, F=1, R=64)["bound"] == "mfma"
+
+
 def test_step_roofline_sums_every_launch():
     prof = {"a": {"ms": 10.0, "launches": 4, "flops": 2e11, "bytes": 1e9},
             "b": {"ms": 30.0, "launches": 2, "flops": 5e11, "bytes": 3e9}}
