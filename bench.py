@@ -53,7 +53,7 @@ def parse():
                     help="metric: the l=1024, 64-field line; mixed: 96 requests of mixed bandlimits "
                          "through the batched persistent launch, beside one call per request; single: "
                          "one complex field at l=256 in FP64 (the factor-streaming regime); orders: the "
-                         "per-order maps of Section 4 for every order of bandlimit --l on "
+                         "per-order maps of Section 5 for every order of bandlimit --l on "
                          "--order-columns columns, forward then inverse")
     ap.add_argument("--order-columns", type=int, default=4, help="R of the orders workload")
     ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
@@ -458,7 +458,7 @@ def mixed(args):
 
 
 def orders(args):
-    """The per-order maps of Section 4 (sht_order_apply): for every order m < 2l and parity p the
+    """The per-order maps of Section 5 (sht_order_apply): for every order m < 2l and parity p the
     n_p x n_p orthogonal matrix of (transform) / (transform2) on its own nodes, butterfly-
     compressed, applied to R columns; one step = the forward map of every pair then the inverse
     (the transposed butterfly).  The oracle applies its dense matrices to the same vectors on a

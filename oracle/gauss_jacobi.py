@@ -1,4 +1,4 @@
-"""Oracle: the per-order quadratures and transforms of Section 4.
+"""Oracle: the per-order quadratures (Section 3.3) and transforms (Section 5).
 
 TEST INFRASTRUCTURE.  Plain, slow, FP64 CPU code; only the tests use it and the library
 shares no code with it.

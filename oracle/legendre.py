@@ -9,7 +9,7 @@ expansions, III"):
 
 * theta grid: the 2l zeros of P_{2l}, ascending (Section 2, equation (thetas)).
 * normalized associated Legendre function, no Condon-Shortley phase
-  (Section 2.3, equation (association)); orthonormal on (-1, 1) for fixed m.
+  (Section 3.3, equation (association)); orthonormal on (-1, 1) for fixed m.
 
 The functions are evaluated by the classical first-order-in-degree (step-one)
 three-term recurrence in its normalized form,
@@ -21,7 +21,7 @@ gives.  This is deliberately not the step-two recurrence (recurrence0) /
 (recurrence) with the coefficients (c_rec) / (d_rec) that the GPU column
 kernel runs: the tests check one against the other.  Underflow of P_m^m at
 large m is countered by carrying a separate integer power-of-two exponent per
-value (the explicit exponent tracking that Section 4 mentions).
+value (the explicit exponent tracking that Section 5 mentions).
 """
 import numpy as np
 

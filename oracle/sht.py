@@ -302,7 +302,7 @@ def synth_adjoint(r, l, kind="complex", grid="fft", direct=False, orders=None, f
 def dense_q(l, m, p):
     """Q[i, j] = sqrt(2 w_i) Pbar^m_{m+p+2j}(x_i) over the l positive nodes (ascending).
 
-    Columns are orthonormal (orthonormality of Section 2.3 plus parity and the
+    Columns are orthonormal (orthonormality of Section 3.3 plus parity and the
     exactness of the Gauss-Legendre rule); this is the analogue on the common
     grid of the paper's unitary per-order maps (transform), (transform2).
     """

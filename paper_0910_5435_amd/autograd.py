@@ -4,7 +4,7 @@ Synthesis is linear in the coefficients, f = S beta, so for a real loss the grad
 respect to the coefficients is the adjoint S^H applied to the gradient with respect to the
 grid.  S^H is the transposed butterfly with the node weights left out, the same factors
 read in the other orientation (the transposition remark after the description of the
-butterfly algorithm, Section 4); the library computes it with ``sht_synth_adjoint``:
+butterfly algorithm, Section 3.2); the library computes it with ``sht_synth_adjoint``:
 
 * complex fields: gamma_k^m = sum_i Pbar_k^|m|(x_i) sum_j g_ij e^{-i m phi_j}, which is the
   gradient in PyTorch's convention for complex leaves (d/dRe + i d/dIm);

@@ -336,7 +336,7 @@ int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nu
 
 namespace {
 
-// Builds and uploads a plan (validated options); maps: the per-order maps of Section 4.
+// Builds and uploads a plan (validated options); maps: the per-order maps of Section 5.
 int make_plan(int l, double eps, const sht_plan_opts& o, bool maps, sht_plan_t* out) {
   int dev = o.device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return SHT_EHIP;

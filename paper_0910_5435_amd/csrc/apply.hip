@@ -1,5 +1,5 @@
 // Butterfly apply kernels: synthesis direction (Q = S * T_L * ... * T_leaf) and the
-// transposed direction that analysis and the adjoint need (Section 2.2 and the remark
+// transposed direction that analysis and the adjoint need (Section 3.2 and the remark
 // after equation (bottom): one factorization serves A and A^T).
 //
 // Data live in R-wide rows: R = 4F for complex fields (re/im of +m and -m per field),
@@ -176,7 +176,7 @@ k_level_trans(const LevelTask* __restrict__ tasks, const double* __restrict__ fa
 
 // ------------------------------------------------------------------------------- final
 // Synthesis: E = S_0 v_0, O = S_1 v_1 on rows [row0, row0+h); g(+x_i) = (E + O)/D_i at
-// ring l + i and g(-x_i) = (E - O)/D_i at ring l - 1 - i (parity, Section 2.3).
+// ring l + i and g(-x_i) = (E - O)/D_i at ring l - 1 - i (parity, Section 3.3).
 template <int RT>
 __global__ void __launch_bounds__(kThreads)
 k_final_synth(const FinalTask* __restrict__ tasks, const double* __restrict__ fac,
@@ -274,7 +274,7 @@ k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
 }
 
 // ------------------------------------------------------------------------- order maps
-// Final of a per-order map A^{(m,p)} (Section 4): y = S w on the task's own output rows, with
+// Final of a per-order map A^{(m,p)} (Section 5): y = S w on the task's own output rows, with
 // neither the parity unfold nor a row scaling (A carries the square roots of its weights).
 template <int RT>
 __global__ void __launch_bounds__(kThreads)

@@ -2,7 +2,7 @@
 // graph capture and the autotuner (declared in include/sht.h).
 //
 // The butterfly of every order m, parity p, field and bandlimit is an independent chain of
-// small interpolations (Section 2.2), so all of them can share the machine at once.  A
+// small interpolations (Section 3.2), so all of them can share the machine at once.  A
 // batch merges the fields of requests that use the same plan into groups (R columns each),
 // turns every (task, column block) of every group into a work item, and orders the items in
 // phases: synthesis runs leaf, levels 1..L, final; the transposed directions run final,

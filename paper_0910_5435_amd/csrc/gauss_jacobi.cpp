@@ -1,4 +1,4 @@
-// The per-order transforms of Section 4 on their own quadratures (host only): for order m,
+// The per-order transforms of Section 5 on their own quadratures (host only): for order m,
 // size n and parity p, the nodes are the n positive zeros of Pbar^m_L, L = m + p + 2n (Lemma
 // distinct_theorem: x_j for p = 0, y_j for p = 1), the weights those of Lemma quadratures,
 // and the n x n matrix of (transform) / (transform2) is
@@ -32,7 +32,7 @@
 // the weights of the rule for (1 - x^2)^m in Lemma quadratures, which stay in range for every
 // m (w alone carries (1 - x^2)^-m).  The rows of A have unit norm, so A[i][j] =
 // R_{m+p+2j}(x_i) / ||(R_{m+p+2k}(x_i))_k||, where the seed factor cancels.  The paper finds
-// its nodes by integrating an ODE in extended precision (Section 4, after its predecessor's
+// its nodes by integrating an ODE in extended precision (Section 5, after its predecessor's
 // Section 3.3); this is a different, standard route.
 #include <algorithm>
 #include <cmath>

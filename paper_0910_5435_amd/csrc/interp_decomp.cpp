@@ -1,16 +1,16 @@
 // Host FP64 precompute: interpolative decompositions and the depth-first
 // butterfly construction.
 //
-// ID (Section 2.1, Remark QR_algorithm): Householder QR with column pivoting
+// ID (Section 3.1, Remark QR_algorithm): Householder QR with column pivoting
 // (largest remaining column norm, lowest index on ties).  After k steps
 // A P = Q [R11 R12; 0 R22]; the skeleton is the first k pivots and
 // T = R11^{-1} R12 gives A[:, red] ~= A[:, skel] T with error ||R22||.  The rank
 // is the least k with ||R22||_F <= eps (Remark adaptivity; the rank property of
-// Section 2.2 measures blocks in the Frobenius norm).  Exchanges of skeleton and
+// Section 3.2 measures blocks in the Frobenius norm).  Exchanges of skeleton and
 // redundant columns then bring every |T_ij| to at most 2, as the Remark requires.
 //
-// Butterfly (Section 2.2, equations (1)-(6), (top), (bottom)) built depth-first
-// (Section 3): only the skeleton columns of unprocessed blocks are kept between
+// Butterfly (Section 3.2, equations (1)-(6), (top), (bottom)) built depth-first
+// (Section 4): only the skeleton columns of unprocessed blocks are kept between
 // merges, so a column chunk is needed once and then dropped.
 #include "interp_decomp.h"
 

@@ -1,6 +1,6 @@
-// Interpolative decomposition by column-pivoted Householder QR (Section 2.1,
+// Interpolative decomposition by column-pivoted Householder QR (Section 3.1,
 // Lemma interpolation_lemma and Remark QR_algorithm), and the multilevel
-// butterfly representation built by the depth-first traversal of Section 3.
+// butterfly representation built by the depth-first traversal of Section 4.
 #pragma once
 
 #include <cstdint>
@@ -60,7 +60,7 @@ class BfTree {
  public:
   BfTree() = default;
   void init(int rows, int cols, int C, int L, double eps);
-  // Depth-first traversal (Section 3): leaf c is constructed only after every
+  // Depth-first traversal (Section 4): leaf c is constructed only after every
   // merge its left neighbours allow has been done.  `leaf` must fill a
   // rows x width column-major array with columns [c*C, c*C + width).
   void add_leaf(int c, const double* chunk, int ld);

@@ -7,7 +7,7 @@
 //   x^2 P_d = d_d P_d + c_d P_{d+2},  d = m, m+1          (recurrence0)
 // with c_d, d_d from (c_rec), (d_rec), seeded by Pbar_m^m and Pbar_{m+1}^m from
 // (association).  Values are carried as mantissa * 2^e (explicit exponent
-// tracking, Section 4) so that seeds far below the FP64 range still grow into
+// tracking, Section 5) so that seeds far below the FP64 range still grow into
 // the band where the functions are O(1).
 //
 // On the common Gauss-Legendre grid the recurrence meets nodes next to the
@@ -19,7 +19,7 @@
 //
 // The recurrence state survives between launches, so the columns are produced
 // leaf chunk by leaf chunk in the order the depth-first precompute consumes
-// them (Section 3).
+// them (Section 4).
 #include "sht_internal.h"
 
 #pragma clang fp contract(off)

@@ -6,7 +6,7 @@
 //     compressed matrices (Remark omission).
 //  2. Columns of Q^{(m,p)} come from the GPU recurrence kernel one leaf chunk at
 //     a time, and each chunk is consumed at once by the depth-first butterfly
-//     construction (Section 3), so no (m, p) ever holds its full matrix.
+//     construction (Section 4), so no (m, p) ever holds its full matrix.
 //  3. The resulting IDs are packed step by step (leaves, then each merge level,
 //     then the final skeletons) so the apply kernels stream them in order; the
 //     factor values go to the device as they are packed.
@@ -192,7 +192,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   double t_cols = 0.0, t_comp = 0.0;
   int err = SHT_OK;
   if (P->maps) {
-    // Per-order maps (Section 4): every A^{(m,p)} on the host (its nodes by Sturm bisection
+    // Per-order maps (Section 5): every A^{(m,p)} on the host (its nodes by Sturm bisection
     // and Newton, its rows by the normalized recurrence), one pair per thread, largest first;
     // the leaves then go to the depth-first construction in column order, as for Q^{(m,p)}.
     std::atomic<int> bad{0};

@@ -1,6 +1,6 @@
 // Plan cache: the butterflies of a plan on disk, one checksummed record per (order, parity),
 // so that a later sht_plan_ex with the same (l, eps, leaf width) skips the precompute of
-// Section 3 (the paper's t_comp, which grows like n^2) and an interrupted build resumes at
+// Section 4 (the paper's t_comp, which grows like n^2) and an interrupted build resumes at
 // the first pair it had not finished.
 //
 // File <cache_dir>/sht_plan_l<l>_C<C>_e<eps bits>_v<format>.cache:

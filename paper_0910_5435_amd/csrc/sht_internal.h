@@ -68,7 +68,7 @@ struct FinalTask {
   I8Off i8[2];        // the same S in the int8-slice pools
 };
 
-// Final skeleton product of one per-order map (Section 4: the n x n matrix A^{(m,p)} of
+// Final skeleton product of one per-order map (Section 5: the n x n matrix A^{(m,p)} of
 // (transform) / (transform2) on its own nodes) and one row node r at level L: y = S w on
 // rows [out_row, out_row + h) of the output, no parity unfold and no row scaling (the
 // square roots of the weights are inside A).
@@ -235,7 +235,7 @@ struct sht_plan_s {
   int device = 0;
   int precision = SHT_FP64;
   int kind = SHT_COMPLEX;
-  bool maps = false;  // a plan of the per-order maps of Section 4 (sht_order_plan), not of the SHT
+  bool maps = false;  // a plan of the per-order maps of Section 5 (sht_order_plan), not of the SHT
   double eps = 0.0;
   std::vector<double> xp, wp;           // positive nodes ascending and their weights
   std::vector<int> n_cols, levels;      // per pair mp = 2m + p

@@ -265,7 +265,7 @@ def _align(ptr):
 
 
 class OrderPlan:
-    """The per-order maps of Section 4 on the GPU (sht_order_plan): for every order m < 2l and
+    """The per-order maps of Section 5 on the GPU (sht_order_plan): for every order m < 2l and
     parity p, the orthogonal n_p x n_p matrix A^{(m,p)} of (transform) / (transform2) on its own
     Gauss-Jacobi-type nodes, butterfly-compressed.  Vectors live in "pair rows": an
     (rows, R) float64 device array in which pair 2m + p owns rows [row0, row0 + n_p)."""
@@ -437,7 +437,7 @@ def plan_cache_append(cache_dir, l, eps, leaf_width, mp, butterfly):
 
 def gauss_jacobi_rule(m, n, parity=0):
     """Nodes x (ascending, positive) and weights lambda = rho (1 - x^2)^m (parity 0) or
-    sigma (1 - x^2)^m (parity 1) of the per-order quadratures of Section 4 (Lemma
+    sigma (1 - x^2)^m (parity 1) of the per-order quadratures of Section 3.3 (Lemma
     quadratures); host only."""
     lib = L.load()
     x = np.empty(int(n))
@@ -457,7 +457,7 @@ def gauss_jacobi_matrix(m, n, parity=0):
 
 
 class Butterfly:
-    """Host-only multilevel ID of a dense matrix (Section 2.2 built per Section 3)."""
+    """Host-only multilevel ID of a dense matrix (Section 3.2 built per Section 4)."""
 
     def __init__(self, a, leaf_width, eps, levels=-1):
         lib = L.load()

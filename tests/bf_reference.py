@@ -1,6 +1,6 @@
 """Test-side application of a host-built butterfly (numpy), used to check the
 library's precompute on the CPU: the operator its factors represent is
-reassembled block by block exactly as Section 2.2 describes and compared with
+reassembled block by block exactly as Section 3.2 describes and compared with
 the dense matrix the oracle provides."""
 import numpy as np
 

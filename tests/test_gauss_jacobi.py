@@ -1,4 +1,4 @@
-"""The per-order transforms of Section 4 on their own quadratures (host only, no GPU):
+"""The per-order transforms of Section 5 on their own quadratures (host only, no GPU):
 the oracle pinned to closed forms, the library against the oracle, and the butterfly of
 the library's matrices against the rank and accuracy figures printed in Tables 1-6."""
 import json
@@ -170,7 +170,7 @@ def test_butterfly_ranks_and_accuracy_match_tables(row):
     assert abs(bf.k_avg - row["k_avg"]) <= 0.1 * row["k_avg"]
     assert abs(bf.k_sd - row["k_sigma"]) <= 0.15 * row["k_sigma"]
     assert 0.75 * row["k_max"] <= bf.k_max <= 1.1 * row["k_max"]
-    # the depth-first construction of Section 3 holds about as many matrix words at its peak
+    # the depth-first construction of Section 4 holds about as many matrix words at its peak
     # as the paper's (0.87x here: the ranks, and so the stored skeleton columns, differ a little)
     assert 0.75 * row["m_max"] <= bf.m_max_words <= 1.1 * row["m_max"]
     assert e_fwd <= 10 * row["eps_fwd"] and e_inv <= 10 * row["eps_inv"]

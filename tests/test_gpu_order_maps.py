@@ -1,4 +1,4 @@
-"""GPU parity of the per-order maps of Section 4 (equations (transform) and (transform2) on the
+"""GPU parity of the per-order maps of Section 5 (equations (transform) and (transform2) on the
 nodes of Lemma distinct_theorem with the weights of Lemma quadratures), applied by the
 butterfly kernels through sht_order_apply, against the oracle's dense matrices
 (oracle.gauss_jacobi.matrix, built on the step-one recurrence and numpy's eigensolver).

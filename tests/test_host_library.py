@@ -229,7 +229,7 @@ def test_factor_entries_count_every_packed_factor(rows, cols, C, levels):
 @pytest.mark.parametrize("l,C,orders", [(64, 8, range(0, 128, 9)), (128, 16, range(0, 256, 31)),
                                          (256, 32, [0, 84, 200, 400])])
 def test_ids_meet_the_remark_qr_bounds(l, C, orders):
-    # Section 2.1, Remark QR_algorithm: every interpolation matrix [I T] (up to column order)
+    # Section 3.1, Remark QR_algorithm: every interpolation matrix [I T] (up to column order)
     # has entries of magnitude <= 2, spectral norm <= sqrt(4k(K-k)+1) and least singular value
     # >= 1, and the ID error in the spectral norm is <= sqrt(4k(K-k)+1) sigma_{k+1} of the
     # block it compresses (checked above rounding level: blocks whose sigma_{k+1} is below
@@ -288,7 +288,7 @@ def test_figure_multi_structure_8x8():
 
 
 def test_depth_first_memory_stays_small():
-    # Section 3: the depth-first traversal holds the current chunk plus the skeleton
+    # Section 4: the depth-first traversal holds the current chunk plus the skeleton
     # columns of unprocessed blocks, far less than the whole matrix.
     # m_max grows like n log n (Remark on the precomputation trends), so its ratio to
     # the n^2 words of the matrix falls as n doubles.

@@ -67,7 +67,7 @@ def _q_c(l, m, p):
 @pytest.mark.parametrize("l,orders,tol", [(40, None, 2e-14), (512, [0, 333, 1023], 5e-13),
                                           (1024, [0, 775, 1500, 2047], 1e-12)])
 def test_c_table_orthonormal_columns(l, orders, tol):
-    # orthonormality of Section 2.3 with parity and the exactness of the Gauss-Legendre rule
+    # orthonormality of Section 3.3 with parity and the exactness of the Gauss-Legendre rule
     for m in (range(2 * l) if orders is None else orders):
         for p in (0, 1):
             Q = _q_c(l, m, p)

@@ -101,7 +101,7 @@ def test_pbar_closed_forms_low_degree(pbar=None):
 
 @pytest.mark.parametrize("m", [0, 1, 7, 120])
 def test_pbar_parity(m, pbar=None):
-    # Section 2.3: Pbar^m_l(-x) = (-1)^(l-m) Pbar^m_l(x).
+    # Section 3.3: Pbar^m_l(-x) = (-1)^(l-m) Pbar^m_l(x).
     x = np.linspace(0.01, 0.99, 37)
     K = m + 400
     Pp = _impl(pbar)([m], x, K)[0]

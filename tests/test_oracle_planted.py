@@ -60,7 +60,7 @@ def _adjoint_without_factor_two(orig):
 
 
 def _odd_perturbation(orig):
-    # a term odd in x slipped into the recurrence (breaks the parity of Section 2.3)
+    # a term odd in x slipped into the recurrence (breaks the parity of Section 3.3)
     def f(orders, x, kmax):
         return orig(orders, x, kmax) * (1.0 + 1e-12 * np.asarray(x))[None, None, :]
     return f
