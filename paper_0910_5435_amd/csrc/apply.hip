@@ -197,7 +197,6 @@ k_final_synth(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
   const int h = ft.h;
   const double* S0 = fac + ft.fac[0];
   const double* S1 = fac + ft.fac[1];
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   for (int e = threadIdx.x; e < h * RT; e += kThreads) {
     const int i = e / RT, c = e % RT;
     double E = 0.0, O = 0.0;
@@ -205,8 +204,8 @@ k_final_synth(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
     for (int a = 0; a < k1; ++a) O = fma(S1[static_cast<long long>(a) * h + i], w1[a * RT + c], O);
     const int row = ft.row0 + i;
     const double s = invD[row];
-    Y[(ybase + l + row) * R + r0 + c] = (E + O) * s;
-    Y[(ybase + l - 1 - row) * R + r0 + c] = (E - O) * s;
+    Y[y_row(l, ft.m, l + row) * R + r0 + c] = (E + O) * s;
+    Y[y_row(l, ft.m, l - 1 - row) * R + r0 + c] = (E - O) * s;
   }
 }
 
@@ -227,7 +226,6 @@ k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
   const int h = ft.h;
   const double* S0 = fac + ft.fac[0];
   const double* S1 = fac + ft.fac[1];
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   for (int g0 = 0; g0 < nout; g0 += kThreads * NACC) {
     double accv[NACC];
 #pragma unroll
@@ -238,8 +236,8 @@ k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fa
       for (int e = threadIdx.x; e < ih * RT; e += kThreads) {
         const int i = e / RT, c = e % RT;
         const int row = ft.row0 + i0 + i;
-        const double gp = Yin[(ybase + l + row) * R + r0 + c];
-        const double gm = Yin[(ybase + l - 1 - row) * R + r0 + c];
+        const double gp = Yin[y_row(l, ft.m, l + row) * R + r0 + c];
+        const double gm = Yin[y_row(l, ft.m, l - 1 - row) * R + r0 + c];
         const double sc = scale[row] * half;
         eo[0][e] = (gp + gm) * sc;
         eo[1][e] = (gp - gm) * sc;

@@ -512,7 +512,6 @@ k_final_synth_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
     i8_cut<NT>(p ? k1 : k0, fv, ecol[p], sets + p * setb);
   }
   __syncthreads();
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   I8Acc acc[2][NTL];
   for (int mt = wave, u = 0; mt < nm;) {
     v4i a[kI8Dig];
@@ -558,8 +557,8 @@ k_final_synth_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
           const int row = ft.row0 + ii;
           const double sc = invD[row];
           const int e0 = ex_of(et0, v), e1 = ex_of(et1, v);
-          double* yp = Y + (ybase + l + row) * R + c0;
-          double* ym = Y + (ybase + l - 1 - row) * R + c0;
+          double* yp = Y + y_row(l, ft.m, l + row) * R + c0;
+          double* ym = Y + y_row(l, ft.m, l - 1 - row) * R + c0;
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
             const int col = n * 16 + lc;
@@ -603,7 +602,6 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
   const int k0 = ft.k[0], k1 = ft.k[1];
   const int h = ft.h;
   const int qh = (h + 63) >> 6;  // contraction chunks of S_p^T
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   double* sums = reinterpret_cast<double*>(lds8);  // rows [0, k0): parity 0, [k0, k0 + k1): parity 1
   double* eo = reinterpret_cast<double*>(lds8 + accb);  // folded chunk: E rows, then O rows
   unsigned char* sets = reinterpret_cast<unsigned char*>(eo + 2 * ICH * LD);
@@ -628,7 +626,7 @@ k_final_trans_i8(const FinalTask* __restrict__ tasks, long long ntasks, int nblk
         ih * NT,
         [&](int e) {
           const int row = ft.row0 + i0 + e / NT, c = e % NT;
-          return make_double2(Yin[(ybase + l + row) * R + c0 + c], Yin[(ybase + l - 1 - row) * R + c0 + c]);
+          return make_double2(Yin[y_row(l, ft.m, l + row) * R + c0 + c], Yin[y_row(l, ft.m, l - 1 - row) * R + c0 + c]);
         },
         [&](int e, double2 g) {
           const int i = e / NT, c = e % NT;

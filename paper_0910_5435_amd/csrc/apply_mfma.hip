@@ -635,7 +635,6 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) bsc[p][n] = PREC == PSPLIT ? colsc[p][lc * NTL + n] : 0;
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   const int nm = (h + 15) >> 4;
   for (int mt = wave; mt < nm; mt += 4) {
     Acc<PREC> E[NTL], O[NTL];
@@ -707,8 +706,8 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
       if (ii < h) {
         const int row = ft.row0 + ii;
         const double s = invD[row];
-        double* yp = Y + (ybase + l + row) * R + c0 + lc * NTL;
-        double* ym = Y + (ybase + l - 1 - row) * R + c0 + lc * NTL;
+        double* yp = Y + y_row(l, ft.m, l + row) * R + c0 + lc * NTL;
+        double* ym = Y + y_row(l, ft.m, l - 1 - row) * R + c0 + lc * NTL;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           const double e = E[n].get(v), od = O[n].get(v);
@@ -753,7 +752,6 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   const long long c0 = static_cast<long long>(blk) * NT;
   double* V = ft.vbuf ? v1buf : v0buf;
   const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
-  const long long ybase = static_cast<long long>(ft.m) * 2 * l;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar registers
   const int lc = lane & 15, lr = lane >> 4;
@@ -774,7 +772,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
         ih * NT,
         [&](int e) {
           const int row = ft.row0 + i0 + e / NT, c = e % NT;
-          return make_double2(Yin[(ybase + l + row) * R + c0 + c], Yin[(ybase + l - 1 - row) * R + c0 + c]);
+          return make_double2(Yin[y_row(l, ft.m, l + row) * R + c0 + c], Yin[y_row(l, ft.m, l - 1 - row) * R + c0 + c]);
         },
         [&](int e, double2 g) {
           const int i = e / NT, c = e % NT;

@@ -4,11 +4,12 @@
 // bit-reversed load, two radix-2 stages per LDS pass (each thread owns a closed set of
 // four points), FP64 throughout.
 //
-// Synthesis reads the Legendre output Y[m][ring][R] (bins +m and -m = N - m) and writes
+// Synthesis reads the Legendre output Y[ring][m][R] (bins +m and -m = N - m) and writes
 // the grid row; analysis reads a grid row and writes the bins back in the same layout,
-// scaled by 1/N (analysis) or 1 (adjoint).  A Y row holds all fields of one (m, ring),
+// scaled by 1/N (analysis) or 1 (adjoint).  A Y row holds all fields of one (ring, m),
 // so work-groups are numbered field-fastest within each XCD: the groups of one ring run
-// together on one XCD and share the L2 lines of their Y gathers and scatters.
+// together on one XCD and share the L2 lines of their Y gathers and scatters, all within
+// that ring's contiguous block of Y.
 #include <atomic>
 
 #include "sht_internal.h"
@@ -95,7 +96,7 @@ __device__ __forceinline__ double* field_grid(double* grid, double* const* fptr,
 }
 
 // One thread per order m: the bins +m and -m of the field sit next to each other in the Y
-// row (m, ring), so they are read together.
+// row (ring, m), so they are read together.
 __global__ void __launch_bounds__(kFftThreads)
 k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* const* __restrict__ fptr,
             const double* __restrict__ tw, int l, int R, int F, int kind) {
@@ -114,7 +115,7 @@ k_fft_synth(const double* __restrict__ Y, double* __restrict__ grid, double* con
       const int m = m0 + u * kFftThreads;
       v[u][0] = v[u][1] = make_double2(0.0, 0.0);
       if (m < L2) {
-        const double* src = Y + (static_cast<long long>(m) * L2 + ring) * R + w * f;
+        const double* src = Y + y_row(l, m, ring) * R + w * f;
         v[u][0] = *reinterpret_cast<const double2*>(src);
         if (kind == SHT_COMPLEX)
           v[u][1] = *reinterpret_cast<const double2*>(src + 2);
@@ -174,7 +175,7 @@ k_fft_analyze(const double* __restrict__ grid, double* const* __restrict__ fptr,
   }
   fft_lds(X, N, logN, tw, -1.0);
   for (int m = threadIdx.x; m < L2; m += kFftThreads) {
-    const long long row = static_cast<long long>(m) * L2 + ring;
+    const long long row = y_row(l, m, ring);
     if (kind == SHT_COMPLEX) {
       double* dst = Y + row * R + 4 * f;
       const double2 p = X[m];

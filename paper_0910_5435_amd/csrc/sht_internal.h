@@ -54,6 +54,13 @@ __host__ __device__ inline long long coeff_pos(int l, int kind, long long ncoef,
   return (static_cast<long long>(f) * ncoef + base + (k - m)) * 2 + c;
 }
 
+// Row of Y (the Legendre output and FFT input, R doubles wide) that holds order m on ring
+// `ring`.  Ring-major: the 2l orders of one ring, which one FFT row reads, form one
+// contiguous block of 2l rows, so an FFT work-group's gather stays within a few pages.
+__host__ __device__ inline long long y_row(int l, int m, int ring) {
+  return static_cast<long long>(ring) * (2LL * l) + m;
+}
+
 // Final skeleton product for one order m and one row node r at level L, both
 // parities at once, followed by the parity unfold g(+-x) = E +- O and the row
 // scaling D^{-1} (synthesis) or its transpose (analysis).
