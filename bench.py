@@ -56,6 +56,8 @@ def parse():
                          "per-order maps of Section 5 for every order of bandlimit --l on "
                          "--order-columns columns, forward then inverse")
     ap.add_argument("--order-columns", type=int, default=4, help="R of the orders workload")
+    ap.add_argument("--host-ids", action="store_true",
+                    help="build the plan's IDs on the host threads instead of on the GPU")
     ap.add_argument("--mixed-bandlimits", default="32,64,128,256,512,1024",
                     help="bandlimits of the mixed workload (uniform draw); the full set 64..2048 needs "
                          "about 210 GB for its inputs and outputs alone")
@@ -578,7 +580,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     t0 = time.perf_counter()
-    plan = Plan(l, eps=args.eps, leaf_width=args.leaf_width, precision=args.precision)
+    plan = Plan(l, eps=args.eps, leaf_width=args.leaf_width, precision=args.precision, id_device=not args.host_ids)
     t_plan = time.perf_counter() - t0
     st = plan.stats()
     print(f"# plan l={l} eps={args.eps} C={args.leaf_width}: {t_plan:.1f} s, k_max={st['k_max']} "
@@ -676,7 +678,7 @@ def main():
         "config": {"workload": f"SHT synthesis+analysis, l={l} (degrees 0..{2 * l - 1}), {F} complex "
                                f"fields, grid {2 * l}x{4 * l}, coefficients CN(0,1)/(1+k)^{args.power}",
                    "l": l, "fields": F, "precision": args.precision, "leaf_width": args.leaf_width,
-                   "eps": args.eps},
+                   "eps": args.eps, "ids_on": "host" if args.host_ids else "gpu"},
         "roofline": roofline(prof, args.precision, l, F),
         "step_roofline": step_roofline(prof, args.steps, ms_step, args.precision, l, F, st["factor_entries"]),
         "variants": variants,

@@ -38,6 +38,7 @@ class PlanOpts(ctypes.Structure):
         ("device", ctypes.c_int),
         ("split_only", ctypes.c_int),
         ("cache_dir", ctypes.c_char_p),
+        ("id_device", ctypes.c_int),
     ]
 
 

@@ -330,6 +330,7 @@ void sht_default_opts(sht_plan_opts* o) {
   o->device = -1;
   o->split_only = 0;
   o->cache_dir = nullptr;
+  o->id_device = 0;
 }
 
 int sht_plan(int l, double eps, sht_plan_t* out) { return sht_plan_ex(l, eps, nullptr, out); }
@@ -407,7 +408,7 @@ int sht_order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out
   if (o.leaf_width == 0) o.leaf_width = 64;
   if (l < 1 || !(eps > 0.0 && eps < 1.0) || o.leaf_width < 2 || o.leaf_width > 4096) return SHT_EINVAL;
   if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
-  if (l > 2048 || o.precision != SHT_FP64 || o.split_only || o.cache_dir) return SHT_EUNSUPPORTED;
+  if (l > 2048 || o.precision != SHT_FP64 || o.split_only || o.cache_dir || o.id_device) return SHT_EUNSUPPORTED;
   return make_plan(l, eps, o, true, out);
 }
 

@@ -295,15 +295,19 @@ int BfTree::leaf_width(int c) const {
   return w > 0 ? static_cast<int>(w) : 0;
 }
 
-void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pending& pend,
-                     const int* gcols) {
-  interp_decomp(a, h, K, lda, eps_, id_, work_);
-  blk.k = id_.k;
+void BfTree::record(IdResult& id, int h, int K, BfBlock& blk, bool take) {
+  blk.k = id.k;
   blk.K = K;
-  blk.skel = id_.skel;
-  blk.red = id_.red;
-  blk.T = id_.T;
-  max_abs_t = std::max(max_abs_t, id_.max_abs_t);
+  if (take) {
+    blk.skel = std::move(id.skel);
+    blk.red = std::move(id.red);
+    blk.T = std::move(id.T);
+  } else {
+    blk.skel = id.skel;
+    blk.red = id.red;
+    blk.T = id.T;
+  }
+  max_abs_t = std::max(max_abs_t, id.max_abs_t);
   factor_entries += static_cast<long long>(blk.T.size());
   k_max = std::max(k_max, blk.k);
   if (K > 0) {  // rank statistics over the blocks that exist (a padded tree has empty slots)
@@ -311,6 +315,63 @@ void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pendi
     sum_k += blk.k;
     sum_k2 += static_cast<double>(blk.k) * blk.k;
   }
+  words_now += static_cast<long long>(h) * blk.k;  // the block's pending skeleton columns
+}
+
+void BfTree::assemble(std::vector<std::vector<IdResult>>& ids, std::vector<std::vector<double>>& S,
+                      std::vector<std::vector<int>>& cols) {
+  if (static_cast<int>(ids.size()) != L_ + 1 || static_cast<int>(S.size()) != (1 << L_) ||
+      static_cast<int>(cols.size()) != (1 << L_))
+    throw std::invalid_argument("BfTree::assemble: shape");
+  for (int t = 0; t <= L_; ++t)
+    if (ids[t].size() != blocks_[t].size()) throw std::invalid_argument("BfTree::assemble: shape");
+  // the depth-first order of add_leaf and merge, with the IDs given instead of computed
+  for (int c = 0; c < (1 << L_); ++c) {
+    const int width = leaf_width(c);
+    const long long chunk_words = static_cast<long long>(rows_) * width;
+    m_max_words = std::max(m_max_words, words_now + chunk_words);
+    IdResult& id = ids[0][c];
+    if (static_cast<int>(id.skel.size() + id.red.size()) != width)
+      throw std::invalid_argument("BfTree::assemble: leaf ID");
+    record(id, rows_, width, blocks_[0][c], true);
+    m_max_words = std::max(m_max_words, words_now + chunk_words);
+    for (int t = 1; t <= L_ && ((c + 1) % (1 << t)) == 0; ++t) {
+      const int cc = c >> t;
+      for (int q = 0; q < nrow(t - 1); ++q) {
+        const int ncp = ncol(t - 1);
+        const int h = row_h_[t - 1][q];
+        const int kL = blocks_[t - 1][q * ncp + 2 * cc].k, kR = blocks_[t - 1][q * ncp + 2 * cc + 1].k;
+        const int K = kL + kR;
+        for (int half = 0; half < 2; ++half) {
+          const int r = 2 * q + half;
+          IdResult& m = ids[t][r * ncol(t) + cc];
+          if (static_cast<int>(m.skel.size() + m.red.size()) != K)
+            throw std::invalid_argument("BfTree::assemble: merged ID");
+          record(m, row_h_[t][r], K, blocks_[t][r * ncol(t) + cc], true);
+          m_max_words = std::max(m_max_words, words_now + static_cast<long long>(h) * K);
+        }
+        words_now -= static_cast<long long>(h) * K;
+      }
+    }
+  }
+  next_leaf_ = 1 << L_;
+  for (int r = 0; r < (1 << L_); ++r) {
+    BfFinal& f = finals_[r];
+    f.row0 = row_lo_[L_][r];
+    f.h = row_h_[L_][r];
+    f.k = blocks_[L_][r].k;
+    if (static_cast<int>(cols[r].size()) != f.k || static_cast<long long>(S[r].size()) != static_cast<long long>(f.h) * f.k)
+      throw std::invalid_argument("BfTree::assemble: final skeleton");
+    f.S = std::move(S[r]);
+    f.cols = std::move(cols[r]);
+    factor_entries += static_cast<long long>(f.S.size());
+  }
+}
+
+void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pending& pend,
+                     const int* gcols) {
+  interp_decomp(a, h, K, lda, eps_, id_, work_);
+  record(id_, h, K, blk);
   pend.vals.resize(static_cast<size_t>(h) * blk.k);
   pend.gcols.resize(blk.k);
   for (int q = 0; q < blk.k; ++q) {
@@ -320,7 +381,6 @@ void BfTree::id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pendi
     pend.gcols[q] = gcols[src];
   }
   pend.live = true;
-  words_now += static_cast<long long>(pend.vals.size());
 }
 
 void BfTree::add_leaf(int c, const double* chunk, int ld) {

@@ -65,6 +65,13 @@ class BfTree {
   // rows x width column-major array with columns [c*C, c*C + width).
   void add_leaf(int c, const double* chunk, int ld);
   bool complete() const { return next_leaf_ == (1 << L_); }
+  // The same tree from IDs computed elsewhere (the device builder): ids[t][r * ncol(t) + c]
+  // for every block (IdResult as interp_decomp returns it), and for every row node r of level
+  // L its final skeleton values S[r] (h x k, column-major) and global columns cols[r].  The
+  // statistics, m_max_words included, come out as the depth-first construction would give
+  // them for the same IDs.  The inputs are moved from.
+  void assemble(std::vector<std::vector<IdResult>>& ids, std::vector<std::vector<double>>& S,
+                std::vector<std::vector<int>>& cols);
 
   int rows() const { return rows_; }
   int cols() const { return cols_; }
@@ -103,6 +110,9 @@ class BfTree {
   void merge(int t, int cc);
   void id_into(const double* a, int h, int K, int lda, BfBlock& blk, Pending& pend,
                const int* gcols);
+  // Stores an ID as block blk and counts it in the statistics (h: the block's rows); take:
+  // move the lists and T out of id instead of copying them.
+  void record(IdResult& id, int h, int K, BfBlock& blk, bool take = false);
 
   int rows_ = 0, cols_ = 0, C_ = 1, L_ = 0;
   double eps_ = 0.0;

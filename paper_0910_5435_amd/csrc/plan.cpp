@@ -228,6 +228,22 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   }
   for (int mp = nvalid; mp < npairs && !P->maps; ++mp)
     trees[mp].init(l, P->n_cols[mp], C, P->levels[mp], P->eps);
+  if (!P->maps && o.id_device && nvalid < npairs) {
+    CacheAppend append;
+    if (cache.is_open())
+      append = [&](int first, int end) {
+        int rc = SHT_OK;
+        for (int mp = first; mp < end && rc == SHT_OK; ++mp) rc = cache.append(mp, trees[mp]);
+        return rc == SHT_OK ? cache.flush() : rc;
+      };
+    try {
+      err = build_trees_on_device(P, trees, nvalid, append, t_cols, t_comp);
+    } catch (const std::bad_alloc&) {
+      err = SHT_ENOMEM;
+    } catch (...) {
+      err = SHT_EINTERNAL;
+    }
+  }
 
   // Device-side column generation, batch by batch.
   const size_t chunk_doubles = static_cast<size_t>(C) * l;
@@ -254,7 +270,7 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   std::unique_ptr<double, void (*)(double*)> host_guard(host_chunk,
                                                           [](double* q) { (void)hipHostFree(q); });
 
-  for (int b0 = 0; b0 < npairs && err == SHT_OK && !P->maps; b0 += batch) {
+  for (int b0 = 0; b0 < npairs && err == SHT_OK && !P->maps && !o.id_device; b0 += batch) {
     const int nb = std::min(batch, npairs - b0);
     if (b0 + nb <= nvalid) continue;  // every butterfly of the batch came from the cache
     std::vector<int> hm(nb), hp(nb), hn(nb);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -345,5 +346,22 @@ hipError_t legendre_seed(ColumnBatch& b, hipStream_t s);
 hipError_t legendre_chunk(ColumnBatch& b, int chunk, hipStream_t s);
 
 void gauss_legendre(int n, double* x, double* w);
+
+// Device-side IDs (id_device.hip).  One block: the h x K submatrix of a pair's Q on rows
+// [row0, row0 + h) and the K global columns listed at gcols.
+struct IdBlockDesc {
+  int64_t q;      // offset of the pair's Q (column-major, leading dimension l) in the Q pool
+  int64_t gcols;  // offset of the K column indices (also of the K output column order)
+  int64_t work;   // offset of the block's h x K scratch
+  int64_t tslot;  // offset of its T slot (K * K / 4 + 1 doubles)
+  int32_t row0, h, K, pad;
+};
+// Appends the butterflies of pairs [first, end) to the plan cache (SHT_OK or a status).
+using CacheAppend = std::function<int(int first, int end)>;
+// Builds trees[first_pair ..] (pair mp = 2m + p of plan P, already sized) with every ID on
+// the device, batch by batch; append (may be empty) runs after each batch.
+class BfTree;
+int build_trees_on_device(sht_plan_s* P, std::vector<BfTree>& trees, int first_pair, CacheAppend append,
+                          double& t_cols, double& t_comp);
 
 }  // namespace sht

@@ -56,7 +56,7 @@ class Plan:
     """Butterfly SHT plan for bandlimit l (degrees 0..2l-1) on one GPU."""
 
     def __init__(self, l, eps=1e-13, leaf_width=64, precision="fp64", kind="complex",
-                 host_threads=0, device=None, split_only=False, cache_dir=None):
+                 host_threads=0, device=None, split_only=False, cache_dir=None, id_device=False):
         lib = L.load()
         opts = L.PlanOpts()
         lib.sht_default_opts(ctypes.byref(opts))
@@ -65,6 +65,7 @@ class Plan:
         opts.field_kind = KINDS[kind]
         opts.host_threads = int(host_threads)
         opts.split_only = 1 if split_only else 0
+        opts.id_device = 1 if id_device else 0
         self._cache_dir = None if cache_dir is None else str(cache_dir).encode()
         opts.cache_dir = self._cache_dir
         if device is None:

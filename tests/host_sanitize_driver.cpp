@@ -2,6 +2,7 @@
 // butterflies of random matrices of many shapes, leaf widths and ranks; the per-order rules
 // and matrices; the Gauss-Legendre rule) in a build with address and undefined-behaviour
 // sanitizers.  Built and run by tests/test_host_library.py; prints "drv ok".
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -27,11 +28,43 @@ int main() {
         A[i + j * rows] = s * std::exp(0.3 * N(g)) + 1e-9 * N(g);
       }
     sht::BfTree t;
-    t.init(rows, cols, C, L, std::pow(10.0, -3.0 - (g() % 11)));
+    const double eps = std::pow(10.0, -3.0 - (g() % 11));
+    t.init(rows, cols, C, L, eps);
     for (int c = 0; c < (1 << L); ++c) {
       const double* chunk = A.data() + (size_t)c * C * rows;
       if (t.leaf_width(c) == 0) chunk = A.data();
       t.add_leaf(c, chunk, rows);
+    }
+    // the same tree assembled from its own IDs and finals (the device builder's path) must
+    // serialise to the same bytes, statistics and depth-first memory figure included
+    std::vector<std::vector<sht::IdResult>> ids(L + 1);
+    for (int lv = 0; lv <= L; ++lv)
+      for (int rr = 0; rr < t.nrow(lv); ++rr)
+        for (int cc = 0; cc < t.ncol(lv); ++cc) {
+          const sht::BfBlock& b = t.block(lv, rr, cc);
+          sht::IdResult id;
+          id.k = b.k;
+          id.skel = b.skel;
+          id.red = b.red;
+          id.T = b.T;
+          for (double v : b.T) id.max_abs_t = std::max(id.max_abs_t, std::fabs(v));
+          ids[lv].push_back(id);
+        }
+    std::vector<std::vector<double>> S;
+    std::vector<std::vector<int>> fc;
+    for (int rr = 0; rr < (1 << L); ++rr) {
+      S.push_back(t.final_block(rr).S);
+      fc.push_back(t.final_block(rr).cols);
+    }
+    sht::BfTree t2;
+    t2.init(rows, cols, C, L, eps);
+    t2.assemble(ids, S, fc);
+    std::vector<unsigned char> a1, a2;
+    t.save(a1);
+    t2.save(a2);
+    if (a1 != a2 || !t2.complete()) {
+      std::printf("assemble mismatch in trial %d\n", trial);
+      return 3;
     }
   }
   // per-order rules and matrices
