@@ -788,46 +788,68 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       cut_block<NT, LD>(eo[1], ih, colsc[1]);
       __syncthreads();
     }
+    // Two output tiles per pass through the rows, so that one tile's matrix instructions
+    // overlap the other's accumulator hand-over (the split form flushes after every K-step);
+    // a tile past the last one repeats the last one's operands and is not stored.
 #pragma unroll
-    for (int u = 0; u < MAXT; ++u) {
-      const int q = t0 + wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
-      if (q >= nm0 + nm1) break;
-      const int p = q < nm0 ? 0 : 1;
-      const int k = p ? k1 : k0;
-      const int a = (p ? q - nm0 : q) * 16 + lc;
-      const long long soff = ft.fac[p];  // S^T: k x h column-major
-      const double* src = eo[p];
-      int bsc[NTL];
+    for (int u = 0; u < MAXT; u += 2) {
+      const int q0 = t0 + wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
+      if (q0 >= nm0 + nm1) break;
+      const int q1 = q0 + 4 < nm0 + nm1 ? q0 + 4 : q0;
+      const int p0 = q0 < nm0 ? 0 : 1, p1 = q1 < nm0 ? 0 : 1;
+      const int kk0 = p0 ? k1 : k0, kk1 = p1 ? k1 : k0;
+      const int a0 = (p0 ? q0 - nm0 : q0) * 16 + lc, a1 = (p1 ? q1 - nm0 : q1) * 16 + lc;
+      const long long so0 = ft.fac[p0], so1 = ft.fac[p1];  // S^T: k x h column-major
+      const double* src0 = eo[p0];
+      const double* src1 = eo[p1];
+      int bs0[NTL], bs1[NTL];
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) bsc[n] = PREC == PSPLIT ? colsc[p][lc * NTL + n] : 0;
-      constexpr int PF = kPrefetch;
+      for (int n = 0; n < NTL; ++n) {
+        bs0[n] = PREC == PSPLIT ? colsc[p0][lc * NTL + n] : 0;
+        bs1[n] = PREC == PSPLIT ? colsc[p1][lc * NTL + n] : 0;
+      }
+      constexpr int PF = kPrefetch / 2;
       const int nsteps = (ih + 3) >> 2;
-      AFrag<PREC> ac[PF], an[PF];
-      auto fetch = [&](int s0, AFrag<PREC>* d) {
+      AFrag<PREC> ac0[PF], an0[PF], ac1[PF], an1[PF];
+      auto fetch = [&](int s0) {
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
-          d[w] = load_a<PREC>(fp, soff + static_cast<long long>(i0 + i) * k + a, i < ih && a < k, soff);
+          an0[w] = load_a<PREC>(fp, so0 + static_cast<long long>(i0 + i) * kk0 + a0, i < ih && a0 < kk0, so0);
+          an1[w] = load_a<PREC>(fp, so1 + static_cast<long long>(i0 + i) * kk1 + a1, i < ih && a1 < kk1, so1);
         }
       };
-      if (nsteps > 0) fetch(0, an);
+      if (nsteps > 0) fetch(0);
       for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
 #pragma unroll
-        for (int w = 0; w < PF; ++w) ac[w] = an[w];
-        if (s0 + PF < nsteps) fetch(s0 + PF, an);
+        for (int w = 0; w < PF; ++w) {
+          ac0[w] = an0[w];
+          ac1[w] = an1[w];
+        }
+        if (s0 + PF < nsteps) fetch(s0 + PF);
         if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
         for (int w = 0; w < PF; ++w) {
           const int i = (s0 + w) * 4 + lr;
           const bool iin = i < ih;
-          const double* er = src + (iin ? i : 0) * LD + lc * NTL;
+          const double* e0 = src0 + (iin ? i : 0) * LD + lc * NTL;
+          const double* e1 = src1 + (iin ? i : 0) * LD + lc * NTL;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n].step(ac[w], b_from<PREC>(er, n, iin, bsc[n]));
+          for (int n = 0; n < NTL; ++n) {
+            acc[u][n].step(ac0[w], b_from<PREC>(e0, n, iin, bs0[n]));
+            acc[u + 1][n].step(ac1[w], b_from<PREC>(e1, n, iin, bs1[n]));
+          }
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) acc[u][n].flush_step();
+          for (int n = 0; n < NTL; ++n) {
+            acc[u][n].flush_step();
+            acc[u + 1][n].flush_step();
+          }
         }
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) acc[u][n].flush();
+        for (int n = 0; n < NTL; ++n) {
+          acc[u][n].flush();
+          acc[u + 1][n].flush();
+        }
       }
     }
   }
