@@ -645,53 +645,45 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
     }
     const int i = mt * 16 + lc;
     const bool iin = i < h;
-    // both parities in one prefetched loop: step s < n0 feeds E, the rest feed O
-    constexpr int PF = kPrefetch;
-    const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 + n1;
+    // both parities in one prefetched loop, interleaved: step st feeds E (rows of S_0) and O
+    // (rows of S_1) at once, two independent accumulator chains per wave
+    constexpr int PF = kPrefetch / 2;
+    const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 > n1 ? n0 : n1;
     const long long safe = k0 > 0 ? ft.fac[0] : ft.fac[1];  // a non-empty block when nsteps > 0
-    AFrag<PREC> ac[PF], an[PF];
-    auto fetch = [&](int s0, AFrag<PREC>* d) {
+    AFrag<PREC> ec[PF], en[PF], oc[PF], on[PF];
+    auto fetch = [&](int s0) {
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
-        const int st = s0 + u;
-        const bool odd = st >= n0;
-        const int a = (odd ? st - n0 : st) * 4 + lr;
-        const bool ain = st < nsteps && a < (odd ? k1 : k0);
-        d[u] = load_a<PREC>(fp, ft.fac[odd ? 1 : 0] + static_cast<long long>(a) * h + i, ain && iin, safe);
+        const int a = (s0 + u) * 4 + lr;
+        en[u] = load_a<PREC>(fp, ft.fac[0] + static_cast<long long>(a) * h + i, a < k0 && iin, safe);
+        on[u] = load_a<PREC>(fp, ft.fac[1] + static_cast<long long>(a) * h + i, a < k1 && iin, safe);
       }
     };
-    if (nsteps > 0) fetch(0, an);
+    if (nsteps > 0) fetch(0);
     for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
 #pragma unroll
-      for (int u = 0; u < PF; ++u) ac[u] = an[u];
-      if (s0 + PF < nsteps) fetch(s0 + PF, an);
+      for (int u = 0; u < PF; ++u) {
+        ec[u] = en[u];
+        oc[u] = on[u];
+      }
+      if (s0 + PF < nsteps) fetch(s0 + PF);
       if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
-        const int st = s0 + u;
-        if (st >= nsteps) break;
-        const bool odd = st >= n0;
-        const int a = (odd ? st - n0 : st) * 4 + lr;
-        const bool ain = a < (odd ? k1 : k0);
-        const double* wr = (odd ? w1 : w0) + (ain ? a : 0) * LD + lc * NTL;
-        if (!odd) {
-          {
-            BFrag<PREC> b[NTL];
-            b_cols<NTL, PREC>(wr, ain, bsc[0], b);
+        const int a = (s0 + u) * 4 + lr;
+        const bool a0 = a < k0, a1 = a < k1;
+        BFrag<PREC> be[NTL], bo[NTL];
+        b_cols<NTL, PREC>(w0 + (a0 ? a : 0) * LD + lc * NTL, a0, bsc[0], be);
+        b_cols<NTL, PREC>(w1 + (a1 ? a : 0) * LD + lc * NTL, a1, bsc[1], bo);
 #pragma unroll
-            for (int n = 0; n < NTL; ++n) E[n].step(ac[u], b[n]);
-          }
+        for (int n = 0; n < NTL; ++n) {
+          E[n].step(ec[u], be[n]);
+          O[n].step(oc[u], bo[n]);
+        }
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) E[n].flush_step();
-        } else {
-          {
-            BFrag<PREC> b[NTL];
-            b_cols<NTL, PREC>(wr, ain, bsc[1], b);
-#pragma unroll
-            for (int n = 0; n < NTL; ++n) O[n].step(ac[u], b[n]);
-          }
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) O[n].flush_step();
+        for (int n = 0; n < NTL; ++n) {
+          E[n].flush_step();
+          O[n].flush_step();
         }
       }
 #pragma unroll
