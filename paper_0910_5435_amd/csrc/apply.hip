@@ -79,250 +79,415 @@ __global__ void k_xin_to_coeff(const PairDesc* __restrict__ pairs, const double*
 }
 
 // ------------------------------------------------------------------------------- levels
-// Synthesis: out_o = in[skel_o] + T_o in[red_o] for the task's one or two outputs.
-// Tasks whose input rows are coefficients (mp >= 0: leaves, level-1 tasks over folded
-// leaves) read them from the internal coefficient rows `xin` instead of `in`.
+// Few columns per (m, p) (R below the matrix-core width): every factor word is used R times,
+// so these launches stream the factors.  One thread owns one output row for all RT columns of
+// the work-group's tile (RT accumulators), and walks the contraction with kUnroll factor
+// loads in flight; consecutive lanes take consecutive rows, so a wave's factor loads are
+// 512 contiguous bytes of a column-major T (synthesis) or of its transposed copy (transposed
+// apply).  The vector operands sit in LDS and are read as broadcasts.
+constexpr int kVecThreads = 128;  // two waves: typically one per output block of a task
+constexpr int kUnroll = 8;
+
+// Synthesis: out_o = in[skel_o] + T_o in[red_o] for the task's one or two outputs.  Tasks
+// whose input rows are coefficients (mp >= 0: leaves) read them from the internal rows `xin`.
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kVecThreads)
 k_level_synth(const LevelTask* __restrict__ tasks, const double* __restrict__ fac,
               const uint16_t* __restrict__ idx, const double* __restrict__ in,
               const double* __restrict__ xin, double* __restrict__ out, int R) {
   extern __shared__ double lds[];
-  const LevelTask tk = tasks[blockIdx.x];
+  const LevelTask& tk = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   const int K = tk.K;
+  const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
   const double* src = tk.mp >= 0 ? xin : in;
-  for (int e = threadIdx.x; e < K * RT; e += kThreads) {
-    const int row = e / RT, c = e % RT;
-    lds[e] = src[(static_cast<long long>(tk.in_row) + row) * R + r0 + c];
+  double* x = lds;                                         // K x RT
+  uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * RT);  // [skel0 red0 | skel1 red1]
+  for (int e = threadIdx.x; e < K * RT; e += kVecThreads)
+    x[e] = src[(static_cast<long long>(tk.in_row) + e / RT) * R + r0 + e % RT];
+  for (int e = threadIdx.x; e < K; e += kVecThreads) {
+    ix[e] = idx[tk.idx[0] + e];
+    if (k1 > 0) ix[K + e] = idx[tk.idx[1] + e];
   }
   __syncthreads();
-  for (int o = 0; o < 2; ++o) {
-    const int k = tk.k[o];
-    if (k <= 0) continue;
-    const uint16_t* skel = idx + tk.idx[o];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nc0 = (k0 + 63) >> 6, nc1 = (k1 + 63) >> 6;
+  for (int it = wave; it < nc0 + nc1; it += kVecThreads / 64) {
+    const int o = it < nc0 ? 0 : 1;
+    const int k = o ? k1 : k0;
+    const int i = (o ? it - nc0 : it) * 64 + lane;
+    if (i >= k) continue;
+    const uint16_t* skel = ix + o * K;
     const uint16_t* red = skel + k;
     const int nr = K - k;
-    const double* T = fac + tk.fac[o];
-    for (int e = threadIdx.x; e < k * RT; e += kThreads) {
-      const int i = e / RT, c = e % RT;
-      double acc = lds[skel[i] * RT + c];
-      for (int j = 0; j < nr; ++j) acc = fma(T[static_cast<long long>(j) * k + i], lds[red[j] * RT + c], acc);
-      out[(static_cast<long long>(tk.out_row[o]) + i) * R + r0 + c] = acc;
+    const double* T = fac + tk.fac[o] + i;  // T (k x nr, column-major): entry (i, j) at j k + i
+    double acc[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) acc[c] = 0.0;
+    int j = 0;
+    for (; j + kUnroll <= nr; j += kUnroll) {
+      double t[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) t[u] = T[static_cast<long long>(j + u) * k];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const double* xr = x + red[j + u] * RT;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[c] = fma(t[u], xr[c], acc[c]);
+      }
     }
+    for (; j < nr; ++j) {
+      const double t = T[static_cast<long long>(j) * k];
+      const double* xr = x + red[j] * RT;
+#pragma unroll
+      for (int c = 0; c < RT; ++c) acc[c] = fma(t, xr[c], acc[c]);
+    }
+    const double* xs = x + skel[i] * RT;
+    double* dst = out + (static_cast<long long>(tk.out_row[o]) + i) * R + r0;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) dst[c] = xs[c] + acc[c];
   }
 }
 
-// Transposed: in = sum_o (Ã_o)^T out_o, where Ã_o has the identity at skel_o and T_o at
-// red_o.  Each input row receives exactly one term from each output block.
+// Transposed: in = sum_o (Ã_o)^T out_o, where Ã_o has the identity at skel_o and T_o at red_o.
+// Each input row receives exactly one term from each output block (its identity row or its
+// T^T row), added into a zeroed LDS block, so the result does not depend on the order.
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kVecThreads)
 k_level_trans(const LevelTask* __restrict__ tasks, const double* __restrict__ fac,
               const uint16_t* __restrict__ idx, const double* __restrict__ win,
               double* __restrict__ xout, double* __restrict__ xin, int R) {
   extern __shared__ double lds[];
-  const LevelTask tk = tasks[blockIdx.x];
+  const LevelTask& tk = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   const int K = tk.K;
   const int k0 = tk.k[0];
   const int k1 = tk.k[1] < 0 ? 0 : tk.k[1];
-  double* w0 = lds;
-  double* w1 = w0 + k0 * RT;
-  double* acc = w1 + k1 * RT;
-  for (int e = threadIdx.x; e < k0 * RT; e += kThreads) {
-    const int row = e / RT, c = e % RT;
-    w0[e] = win[(static_cast<long long>(tk.out_row[0]) + row) * R + r0 + c];
-  }
-  for (int e = threadIdx.x; e < k1 * RT; e += kThreads) {
-    const int row = e / RT, c = e % RT;
-    w1[e] = win[(static_cast<long long>(tk.out_row[1]) + row) * R + r0 + c];
+  const int nouts = tk.k[1] < 0 ? 1 : 2;
+  double* acc_l = lds;              // K x RT
+  double* w0 = acc_l + K * RT;      // k0 x RT
+  double* w1 = w0 + k0 * RT;        // k1 x RT
+  uint16_t* ix = reinterpret_cast<uint16_t*>(w1 + k1 * RT);
+  for (int e = threadIdx.x; e < K * RT; e += kVecThreads) acc_l[e] = 0.0;
+  for (int e = threadIdx.x; e < k0 * RT; e += kVecThreads)
+    w0[e] = win[(static_cast<long long>(tk.out_row[0]) + e / RT) * R + r0 + e % RT];
+  for (int e = threadIdx.x; e < k1 * RT; e += kVecThreads)
+    w1[e] = win[(static_cast<long long>(tk.out_row[1]) + e / RT) * R + r0 + e % RT];
+  for (int e = threadIdx.x; e < K; e += kVecThreads) {
+    ix[e] = idx[tk.idx[0] + e];
+    if (nouts > 1) ix[K + e] = idx[tk.idx[1] + e];
   }
   __syncthreads();
-  const int nouts = tk.k[1] < 0 ? 1 : 2;
+  // identity rows
   for (int o = 0; o < nouts; ++o) {
     const int k = o ? k1 : k0;
     const double* w = o ? w1 : w0;
-    const uint16_t* skel = idx + tk.idx[o];
-    const uint16_t* red = skel + k;
-    const double* T = fac + tk.fac[o];
-    for (int e = threadIdx.x; e < K * RT; e += kThreads) {
-      const int q = e / RT, c = e % RT;
-      int dst;
-      double v;
-      if (q < k) {
-        dst = skel[q];
-        v = w[q * RT + c];
-      } else {
-        // T^T stored column-major (nr x k): entry (j, i) at i * nr + j
-        const int j = q - k;
-        const int nr = K - k;
-        dst = red[j];
-        v = 0.0;
-        for (int i = 0; i < k; ++i) v = fma(T[static_cast<long long>(i) * nr + j], w[i * RT + c], v);
+    const uint16_t* skel = ix + o * K;
+    for (int e = threadIdx.x; e < k * RT; e += kVecThreads)
+      atomicAdd(acc_l + skel[e / RT] * RT + e % RT, w[e]);
+  }
+  // T^T rows: one thread per redundant column j of an output, summed over that output's rows
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nr0 = K - k0, nr1 = nouts > 1 ? K - k1 : 0;
+  const int nc0 = (nr0 + 63) >> 6, nc1 = (nr1 + 63) >> 6;
+  for (int it = wave; it < nc0 + nc1; it += kVecThreads / 64) {
+    const int o = it < nc0 ? 0 : 1;
+    const int k = o ? k1 : k0;
+    const int nr = o ? nr1 : nr0;
+    const int j = (o ? it - nc0 : it) * 64 + lane;
+    if (j >= nr) continue;
+    const double* w = o ? w1 : w0;
+    const double* Tt = fac + tk.fac[o] + j;  // T^T (nr x k, column-major): entry (j, i) at i nr + j
+    double acc[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) acc[c] = 0.0;
+    int i = 0;
+    for (; i + kUnroll <= k; i += kUnroll) {
+      double t[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) t[u] = Tt[static_cast<long long>(i + u) * nr];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const double* wr = w + (i + u) * RT;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[c] = fma(t[u], wr[c], acc[c]);
       }
-      if (o == 0)
-        acc[dst * RT + c] = v;
-      else
-        acc[dst * RT + c] += v;
     }
-    __syncthreads();
+    for (; i < k; ++i) {
+      const double t = Tt[static_cast<long long>(i) * nr];
+      const double* wr = w + i * RT;
+#pragma unroll
+      for (int c = 0; c < RT; ++c) acc[c] = fma(t, wr[c], acc[c]);
+    }
+    double* d = acc_l + ix[o * K + k + j] * RT;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) atomicAdd(d + c, acc[c]);
   }
+  __syncthreads();
   double* dst = tk.mp >= 0 ? xin : xout;
-  for (int e = threadIdx.x; e < K * RT; e += kThreads) {
-    const int row = e / RT, c = e % RT;
-    dst[(static_cast<long long>(tk.in_row) + row) * R + r0 + c] = acc[e];
-  }
+  for (int e = threadIdx.x; e < K * RT; e += kVecThreads)
+    dst[(static_cast<long long>(tk.in_row) + e / RT) * R + r0 + e % RT] = acc_l[e];
 }
 
 // ------------------------------------------------------------------------------- final
 // Synthesis: E = S_0 v_0, O = S_1 v_1 on rows [row0, row0+h); g(+x_i) = (E + O)/D_i at
-// ring l + i and g(-x_i) = (E - O)/D_i at ring l - 1 - i (parity, Section 3.3).
+// ring l + i and g(-x_i) = (E - O)/D_i at ring l - 1 - i (parity, Section 3.3).  One thread
+// per row with both parities and all RT columns in registers; when the task has fewer row
+// chunks of 64 than the work-group has waves, each chunk's contraction is split over
+// several waves, whose partial sums are added in a fixed order (results do not depend on
+// the schedule).
+constexpr int kFinThreads = 256;
+constexpr int kFinWaves = kFinThreads / 64;
+
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_final_synth(const FinalTask* __restrict__ tasks, const double* __restrict__ fac,
               const double* __restrict__ v0buf, const double* __restrict__ v1buf,
               const double* __restrict__ invD, double* __restrict__ Y, int l, int R) {
   extern __shared__ double lds[];
-  const FinalTask ft = tasks[blockIdx.x];
+  const FinalTask& ft = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   const double* V = ft.vbuf ? v1buf : v0buf;
-  const int k0 = ft.k[0], k1 = ft.k[1];
+  const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
+  const int nch = (h + 63) >> 6;
+  const int nparts = nch >= kFinWaves ? 1 : kFinWaves / nch;
   double* w0 = lds;
   double* w1 = lds + k0 * RT;
-  for (int e = threadIdx.x; e < k0 * RT; e += kThreads)
+  double* part = w1 + k1 * RT;  // [part][row][E | O][RT] when nparts > 1
+  for (int e = threadIdx.x; e < k0 * RT; e += kFinThreads)
     w0[e] = V[(static_cast<long long>(ft.in_row[0]) + e / RT) * R + r0 + e % RT];
-  for (int e = threadIdx.x; e < k1 * RT; e += kThreads)
+  for (int e = threadIdx.x; e < k1 * RT; e += kFinThreads)
     w1[e] = V[(static_cast<long long>(ft.in_row[1]) + e / RT) * R + r0 + e % RT];
   __syncthreads();
-  const int h = ft.h;
-  const double* S0 = fac + ft.fac[0];
-  const double* S1 = fac + ft.fac[1];
-  for (int e = threadIdx.x; e < h * RT; e += kThreads) {
-    const int i = e / RT, c = e % RT;
-    double E = 0.0, O = 0.0;
-    for (int a = 0; a < k0; ++a) E = fma(S0[static_cast<long long>(a) * h + i], w0[a * RT + c], E);
-    for (int a = 0; a < k1; ++a) O = fma(S1[static_cast<long long>(a) * h + i], w1[a * RT + c], O);
+  // A += S w over columns [a0, a1) of one parity (S: h x k, column-major; this thread's row)
+  auto accum = [&](const double* S, const double* w, int a0, int a1, double (&A)[RT]) {
+    int a = a0;
+    for (; a + kUnroll <= a1; a += kUnroll) {
+      double t[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) t[u] = S[static_cast<long long>(a + u) * h];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int c = 0; c < RT; ++c) A[c] = fma(t[u], w[(a + u) * RT + c], A[c]);
+    }
+    for (; a < a1; ++a) {
+      const double t = S[static_cast<long long>(a) * h];
+#pragma unroll
+      for (int c = 0; c < RT; ++c) A[c] = fma(t, w[a * RT + c], A[c]);
+    }
+  };
+  auto store = [&](int i, const double* E, const double* O) {
     const int row = ft.row0 + i;
     const double s = invD[row];
-    Y[y_row(l, ft.m, l + row) * R + r0 + c] = (E + O) * s;
-    Y[y_row(l, ft.m, l - 1 - row) * R + r0 + c] = (E - O) * s;
+    double* yp = Y + y_row(l, ft.m, l + row) * R + r0;
+    double* ym = Y + y_row(l, ft.m, l - 1 - row) * R + r0;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) {
+      yp[c] = (E[c] + O[c]) * s;
+      ym[c] = (E[c] - O[c]) * s;
+    }
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = wave; it < nch * nparts; it += kFinWaves) {
+    const int ch = it / nparts, pt = it % nparts;
+    const int i = ch * 64 + lane;
+    if (i >= h) continue;
+    double E[RT], O[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) E[c] = O[c] = 0.0;
+    accum(fac + ft.fac[0] + i, w0, k0 * pt / nparts, k0 * (pt + 1) / nparts, E);
+    accum(fac + ft.fac[1] + i, w1, k1 * pt / nparts, k1 * (pt + 1) / nparts, O);
+    if (nparts == 1) {
+      store(i, E, O);
+    } else {
+      double* d = part + (static_cast<long long>(pt) * h + i) * 2 * RT;
+#pragma unroll
+      for (int c = 0; c < RT; ++c) {
+        d[c] = E[c];
+        d[RT + c] = O[c];
+      }
+    }
+  }
+  if (nparts == 1) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < h; i += kFinThreads) {
+    double E[RT], O[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) E[c] = O[c] = 0.0;
+    for (int pt = 0; pt < nparts; ++pt) {
+      const double* d = part + (static_cast<long long>(pt) * h + i) * 2 * RT;
+#pragma unroll
+      for (int c = 0; c < RT; ++c) {
+        E[c] += d[c];
+        O[c] += d[RT + c];
+      }
+    }
+    store(i, E, O);
   }
 }
 
-// Transposed: v_p = S_p^T (scale * half * (G(+x) +- G(-x))).
+// Transposed: v_p = S_p^T (scale * half * (G(+x) +- G(-x))): the folded rows of the task in
+// LDS, one thread per output row a of either parity, summing over the task's rows.
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_final_trans(const FinalTask* __restrict__ tasks, const double* __restrict__ fac,
               const double* __restrict__ Yin, const double* __restrict__ scale, double half,
               double* __restrict__ v0buf, double* __restrict__ v1buf, int l, int R) {
-  constexpr int ICH = 64;
-  constexpr int NACC = 8;
-  __shared__ double eo[2][ICH * RT];
-  const FinalTask ft = tasks[blockIdx.x];
+  extern __shared__ double lds[];
+  const FinalTask& ft = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   double* V = ft.vbuf ? v1buf : v0buf;
-  const int k0 = ft.k[0], k1 = ft.k[1];
-  const int nout = (k0 + k1) * RT;
-  const int h = ft.h;
-  const double* S0 = fac + ft.fac[0];
-  const double* S1 = fac + ft.fac[1];
-  for (int g0 = 0; g0 < nout; g0 += kThreads * NACC) {
-    double accv[NACC];
+  const int k0 = ft.k[0], k1 = ft.k[1], h = ft.h;
+  double* eo0 = lds;           // h x RT, even part
+  double* eo1 = lds + h * RT;  // h x RT, odd part
+  for (int e = threadIdx.x; e < h * RT; e += kFinThreads) {
+    const int i = e / RT, c = e % RT;
+    const int row = ft.row0 + i;
+    const double gp = Yin[y_row(l, ft.m, l + row) * R + r0 + c];
+    const double gm = Yin[y_row(l, ft.m, l - 1 - row) * R + r0 + c];
+    const double sc = scale[row] * half;
+    eo0[e] = (gp + gm) * sc;
+    eo1[e] = (gp - gm) * sc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < k0 + k1; q += kFinThreads) {
+    const int p = q < k0 ? 0 : 1;
+    const int a = p ? q - k0 : q;
+    const int k = p ? k1 : k0;
+    const double* St = fac + ft.fac[p] + a;  // S^T (k x h, column-major): entry (a, i) at i k + a
+    const double* src = p ? eo1 : eo0;
+    double acc[RT];
 #pragma unroll
-    for (int u = 0; u < NACC; ++u) accv[u] = 0.0;
-    for (int i0 = 0; i0 < h; i0 += ICH) {
-      const int ih = min(ICH, h - i0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < ih * RT; e += kThreads) {
-        const int i = e / RT, c = e % RT;
-        const int row = ft.row0 + i0 + i;
-        const double gp = Yin[y_row(l, ft.m, l + row) * R + r0 + c];
-        const double gm = Yin[y_row(l, ft.m, l - 1 - row) * R + r0 + c];
-        const double sc = scale[row] * half;
-        eo[0][e] = (gp + gm) * sc;
-        eo[1][e] = (gp - gm) * sc;
-      }
-      __syncthreads();
+    for (int c = 0; c < RT; ++c) acc[c] = 0.0;
+    int i = 0;
+    for (; i + kUnroll <= h; i += kUnroll) {
+      double t[kUnroll];
 #pragma unroll
-      for (int u = 0; u < NACC; ++u) {
-        const int e = g0 + u * kThreads + threadIdx.x;
-        if (e >= nout) continue;
-        const int q = e / RT, c = e % RT;
-        const int p = q < k0 ? 0 : 1;
-        const int a = p ? q - k0 : q;
-        // S^T stored column-major (k x h): entry (a, i) at i * k + a
-        const int kp = p ? k1 : k0;
-        const double* Sa = (p ? S1 : S0) + static_cast<long long>(i0) * kp + a;
-        const double* src = eo[p];
-        double v = accv[u];
-        for (int i = 0; i < ih; ++i) v = fma(Sa[static_cast<long long>(i) * kp], src[i * RT + c], v);
-        accv[u] = v;
-      }
+      for (int u = 0; u < kUnroll; ++u) t[u] = St[static_cast<long long>(i + u) * k];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[c] = fma(t[u], src[(i + u) * RT + c], acc[c]);
     }
+    for (; i < h; ++i) {
+      const double t = St[static_cast<long long>(i) * k];
 #pragma unroll
-    for (int u = 0; u < NACC; ++u) {
-      const int e = g0 + u * kThreads + threadIdx.x;
-      if (e >= nout) continue;
-      const int q = e / RT, c = e % RT;
-      const int p = q < k0 ? 0 : 1;
-      const int a = p ? q - k0 : q;
-      V[(static_cast<long long>(ft.in_row[p]) + a) * R + r0 + c] = accv[u];
+      for (int c = 0; c < RT; ++c) acc[c] = fma(t, src[i * RT + c], acc[c]);
     }
+    double* dst = V + (static_cast<long long>(ft.in_row[p]) + a) * R + r0;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) dst[c] = acc[c];
   }
 }
 
 // ------------------------------------------------------------------------- order maps
 // Final of a per-order map A^{(m,p)} (Section 5): y = S w on the task's own output rows, with
 // neither the parity unfold nor a row scaling (A carries the square roots of its weights).
+// Laid out like the spherical finals above: one thread per output row (synthesis) or per
+// output column of S^T (transposed), RT columns in registers, short contractions split over
+// waves with fixed-order partial sums.
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_order_final_synth(const OrderFinal* __restrict__ tasks, const double* __restrict__ fac,
                     const double* __restrict__ v0buf, const double* __restrict__ v1buf,
                     double* __restrict__ y, int R) {
   extern __shared__ double lds[];
-  const OrderFinal ft = tasks[blockIdx.x];
+  const OrderFinal& ft = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   const double* V = ft.vbuf ? v1buf : v0buf;
   const int k = ft.k, h = ft.h;
-  for (int e = threadIdx.x; e < k * RT; e += kThreads)
-    lds[e] = V[(static_cast<long long>(ft.in_row) + e / RT) * R + r0 + e % RT];
+  const int nch = (h + 63) >> 6;
+  const int nparts = nch >= kFinWaves ? 1 : kFinWaves / nch;
+  double* w = lds;           // k x RT
+  double* part = w + k * RT;  // [part][row][RT] when nparts > 1
+  for (int e = threadIdx.x; e < k * RT; e += kFinThreads)
+    w[e] = V[(static_cast<long long>(ft.in_row) + e / RT) * R + r0 + e % RT];
   __syncthreads();
-  const double* S = fac + ft.fac;  // h x k, column-major
-  for (int e = threadIdx.x; e < h * RT; e += kThreads) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = wave; it < nch * nparts; it += kFinWaves) {
+    const int ch = it / nparts, pt = it % nparts;
+    const int i = ch * 64 + lane;
+    if (i >= h) continue;
+    const double* S = fac + ft.fac + i;  // h x k, column-major
+    double acc[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) acc[c] = 0.0;
+    const int a1 = k * (pt + 1) / nparts;
+    int a = k * pt / nparts;
+    for (; a + kUnroll <= a1; a += kUnroll) {
+      double t[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) t[u] = S[static_cast<long long>(a + u) * h];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[c] = fma(t[u], w[(a + u) * RT + c], acc[c]);
+    }
+    for (; a < a1; ++a) {
+      const double t = S[static_cast<long long>(a) * h];
+#pragma unroll
+      for (int c = 0; c < RT; ++c) acc[c] = fma(t, w[a * RT + c], acc[c]);
+    }
+    double* d = nparts == 1 ? y + (static_cast<long long>(ft.out_row) + i) * R + r0
+                            : part + (static_cast<long long>(pt) * h + i) * RT;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) d[c] = acc[c];
+  }
+  if (nparts == 1) return;
+  __syncthreads();
+  for (int e = threadIdx.x; e < h * RT; e += kFinThreads) {
     const int i = e / RT, c = e % RT;
-    double acc = 0.0;
-    for (int a = 0; a < k; ++a) acc = fma(S[static_cast<long long>(a) * h + i], lds[a * RT + c], acc);
-    y[(static_cast<long long>(ft.out_row) + i) * R + r0 + c] = acc;
+    double v = 0.0;
+    for (int pt = 0; pt < nparts; ++pt) v += part[(static_cast<long long>(pt) * h + i) * RT + c];
+    y[(static_cast<long long>(ft.out_row) + i) * R + r0 + c] = v;
   }
 }
 
 // Transposed: w = S^T y, from the transposed pool (S^T is k x h column-major there).
 template <int RT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_order_final_trans(const OrderFinal* __restrict__ tasks, const double* __restrict__ fac_t,
                     const double* __restrict__ yin, double* __restrict__ v0buf,
                     double* __restrict__ v1buf, int R) {
   extern __shared__ double lds[];
-  const OrderFinal ft = tasks[blockIdx.x];
+  const OrderFinal& ft = tasks[blockIdx.x];
   const int r0 = blockIdx.y * RT;
   double* V = ft.vbuf ? v1buf : v0buf;
   const int k = ft.k, h = ft.h;
-  for (int e = threadIdx.x; e < h * RT; e += kThreads)
+  for (int e = threadIdx.x; e < h * RT; e += kFinThreads)
     lds[e] = yin[(static_cast<long long>(ft.out_row) + e / RT) * R + r0 + e % RT];
   __syncthreads();
-  const double* St = fac_t + ft.fac;
-  for (int e = threadIdx.x; e < k * RT; e += kThreads) {
-    const int a = e / RT, c = e % RT;
-    double acc = 0.0;
-    for (int i = 0; i < h; ++i) acc = fma(St[static_cast<long long>(i) * k + a], lds[i * RT + c], acc);
-    V[(static_cast<long long>(ft.in_row) + a) * R + r0 + c] = acc;
+  for (int a = threadIdx.x; a < k; a += kFinThreads) {
+    const double* St = fac_t + ft.fac + a;  // entry (a, i) at i k + a
+    double acc[RT];
+#pragma unroll
+    for (int c = 0; c < RT; ++c) acc[c] = 0.0;
+    int i = 0;
+    for (; i + kUnroll <= h; i += kUnroll) {
+      double t[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) t[u] = St[static_cast<long long>(i + u) * k];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[c] = fma(t[u], lds[(i + u) * RT + c], acc[c]);
+    }
+    for (; i < h; ++i) {
+      const double t = St[static_cast<long long>(i) * k];
+#pragma unroll
+      for (int c = 0; c < RT; ++c) acc[c] = fma(t, lds[i * RT + c], acc[c]);
+    }
+    double* dst = V + (static_cast<long long>(ft.in_row) + a) * R + r0;
+#pragma unroll
+    for (int c = 0; c < RT; ++c) dst[c] = acc[c];
   }
 }
 
-// Largest column tile (<= 16) that divides R and keeps the LDS footprint of
+// Largest column tile (<= 8) that divides R and keeps the LDS footprint of
 // `per_col` doubles per column within 64 KiB.
 int pick_rt(int R, long long per_col) {
-  int rt = 16;
+  int rt = 8;
   while (rt > 1 && (R % rt != 0 || per_col * rt * 8 > 65536)) rt >>= 1;
   return rt;
 }
@@ -356,19 +521,20 @@ hipError_t launch_level(const sht_plan_s* P, int step, bool transpose, const dou
   const LevelTask* tasks = P->d.tasks + P->step_off[step];
   const int K = P->step_maxK[step], k = P->step_maxk[step];
   const int RT = pick_rt(R, transpose ? K + 2 * k : K);
+  if (R / RT > 65535) return hipErrorInvalidConfiguration;
   dim3 grid(static_cast<unsigned>(cnt), R / RT);
-  const size_t lds = transpose ? sizeof(double) * RT * (K + 2 * k) : sizeof(double) * RT * K;
+  // vectors (and, transposed, the accumulated input block) plus the two index lists
+  const size_t lds = sizeof(double) * RT * (transpose ? K + 2 * k : K) + 4 * static_cast<size_t>(K) + 16;
 #define LAUNCH_LEVEL(RTV)                                                                       \
   do {                                                                                           \
     if (transpose)                                                                               \
-      hipLaunchKernelGGL(k_level_trans<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac_t,    \
+      hipLaunchKernelGGL(k_level_trans<RTV>, grid, dim3(kVecThreads), lds, s, tasks, P->d.fac_t, \
                          P->d.idx, in, out, xin, R);                                             \
     else                                                                                         \
-      hipLaunchKernelGGL(k_level_synth<RTV>, grid, dim3(kThreads), lds, s, tasks, P->d.fac,      \
+      hipLaunchKernelGGL(k_level_synth<RTV>, grid, dim3(kVecThreads), lds, s, tasks, P->d.fac,   \
                          P->d.idx, in, xin, out, R);                                             \
   } while (0)
   switch (RT) {
-    case 16: LAUNCH_LEVEL(16); break;
     case 8: LAUNCH_LEVEL(8); break;
     case 4: LAUNCH_LEVEL(4); break;
     case 2: LAUNCH_LEVEL(2); break;
@@ -385,22 +551,25 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
   if (mfma_ok(R))
     return launch_final_mfma(P, transpose, v0, v1, v0w, v1w, y, yin, R, precision, adjoint, s, cls);
   if (precision != SHT_FP64) return hipErrorNotSupported;
-  const int RT = pick_rt(R, std::max(2LL * P->final_maxk, 64LL * 2));
+  // per column: the folded rows (transposed) or the two input blocks plus the partial sums of a
+  // split contraction (at most kFinWaves parts of 64 rows, E and O)
+  const long long rows = transpose ? 2LL * P->final_maxh : 2LL * P->final_maxk + 2LL * kFinThreads;
+  const int RT = pick_rt(R, std::max(rows, 1LL));
+  if (rows * RT * 8 > 65536 || R / RT > 65535) return hipErrorInvalidConfiguration;
   dim3 grid(static_cast<unsigned>(P->n_final), R / RT);
-  const size_t lds = sizeof(double) * RT * 2 * P->final_maxk;
+  const size_t lds = sizeof(double) * RT * std::max(rows, 1LL);
   const double* scale = adjoint ? P->d.invD : P->d.D;
   const double half = adjoint ? 1.0 : 0.5;
 #define LAUNCH_FINAL(RTV)                                                                       \
   do {                                                                                           \
     if (transpose)                                                                               \
-      hipLaunchKernelGGL(k_final_trans<RTV>, grid, dim3(kThreads), 0, s, P->d.finals, P->d.fac_t,\
-                         yin, scale, half, v0w, v1w, P->l, R);                                   \
+      hipLaunchKernelGGL(k_final_trans<RTV>, grid, dim3(kFinThreads), lds, s, P->d.finals,        \
+                         P->d.fac_t, yin, scale, half, v0w, v1w, P->l, R);                       \
     else                                                                                         \
-      hipLaunchKernelGGL(k_final_synth<RTV>, grid, dim3(kThreads), lds, s, P->d.finals,          \
+      hipLaunchKernelGGL(k_final_synth<RTV>, grid, dim3(kFinThreads), lds, s, P->d.finals,        \
                          P->d.fac, v0, v1, P->d.invD, y, P->l, R);                               \
   } while (0)
   switch (RT) {
-    case 16: LAUNCH_FINAL(16); break;
     case 8: LAUNCH_FINAL(8); break;
     case 4: LAUNCH_FINAL(4); break;
     case 2: LAUNCH_FINAL(2); break;
@@ -413,7 +582,8 @@ hipError_t launch_final(const sht_plan_s* P, bool transpose, const double* v0, c
 hipError_t launch_order_final(const sht_plan_s* P, bool transpose, const double* v0, const double* v1,
                               double* v0w, double* v1w, double* y, const double* yin, int R, hipStream_t s) {
   if (P->n_ofinal == 0) return hipSuccess;
-  const long long rows = std::max(1, transpose ? P->ofinal_maxh : P->ofinal_maxk);
+  // per column: the staged rows (transposed) or the input block plus split partial sums
+  const long long rows = transpose ? std::max(1, P->ofinal_maxh) : P->ofinal_maxk + kFinThreads;
   const int RT = pick_rt(R, rows);
   if (rows * RT * 8 > 65536 || R / RT > 65535) return hipErrorInvalidConfiguration;
   dim3 grid(static_cast<unsigned>(P->n_ofinal), R / RT);
@@ -421,14 +591,13 @@ hipError_t launch_order_final(const sht_plan_s* P, bool transpose, const double*
 #define LAUNCH_OFINAL(RTV)                                                                           \
   do {                                                                                                \
     if (transpose)                                                                                    \
-      hipLaunchKernelGGL(k_order_final_trans<RTV>, grid, dim3(kThreads), lds, s, P->d.ofinals,        \
+      hipLaunchKernelGGL(k_order_final_trans<RTV>, grid, dim3(kFinThreads), lds, s, P->d.ofinals,     \
                          P->d.fac_t, yin, v0w, v1w, R);                                               \
     else                                                                                              \
-      hipLaunchKernelGGL(k_order_final_synth<RTV>, grid, dim3(kThreads), lds, s, P->d.ofinals,        \
+      hipLaunchKernelGGL(k_order_final_synth<RTV>, grid, dim3(kFinThreads), lds, s, P->d.ofinals,     \
                          P->d.fac, v0, v1, y, R);                                                     \
   } while (0)
   switch (RT) {
-    case 16: LAUNCH_OFINAL(16); break;
     case 8: LAUNCH_OFINAL(8); break;
     case 4: LAUNCH_OFINAL(4); break;
     case 2: LAUNCH_OFINAL(2); break;
