@@ -326,7 +326,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
     // factor fragments are fetched PF K-steps ahead (double-buffered in registers), and with
     // them the LDS row offsets of the gathered vector rows, so that a K-step waits on one LDS
     // read instead of two dependent ones
-    constexpr int PF = kPrefetch;
+    constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
     const int nsteps = (nr + 3) >> 2;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
     int roc[PF], ron[PF];
@@ -485,7 +485,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
 #pragma unroll
       for (int n = 0; n < NTL; ++n) acc[u][n].zero();
     const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
-    constexpr int PF = kPrefetch;
+    constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
     const int nsteps = (k + 3) >> 2;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
     constexpr int PB = WLDS ? 1 : PF;  // B fragments prefetched with A when read from global
@@ -647,7 +647,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
     const bool iin = i < h;
     // both parities in one prefetched loop, interleaved: step st feeds E (rows of S_0) and O
     // (rows of S_1) at once, two independent accumulator chains per wave
-    constexpr int PF = kPrefetch / 2;
+    constexpr int PF = PIN ? kPrefetch / 2 : kPrefetch / 4;
     const int n0 = (k0 + 3) >> 2, n1 = (k1 + 3) >> 2, nsteps = n0 > n1 ? n0 : n1;
     const long long safe = k0 > 0 ? ft.fac[0] : ft.fac[1];  // a non-empty block when nsteps > 0
     AFrag<PREC> ec[PF], en[PF], oc[PF], on[PF];
@@ -730,14 +730,15 @@ k_final_synth_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
 template <int NT, int ICH>
 constexpr size_t final_trans_lds() { return 2 * ICH * ldp<NT>() * sizeof(double); }
 
-template <int NT, int ICH, int PREC, bool PIN = true>
+template <int NT, int ICH, int PREC, bool PIN = true, int MAXT = 6>
 __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
                                  const double* __restrict__ Yin, const double* __restrict__ scale,
                                  double half, double* __restrict__ v0buf, double* __restrict__ v1buf,
                                  int l, int R, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  constexpr int MAXT = 6;  // row tiles per wave and pass: a pass covers 4 MAXT tiles (384 rows)
+  // MAXT: output tiles per wave and pass (a pass covers 4 MAXT tiles; 6: 384 rows); even
+  static_assert(MAXT % 2 == 0, "output tiles go through the rows in pairs");
   double* eo[2] = {lds, lds + ICH * LD};
   __shared__ double red_s[256];
   __shared__ int colsc[2][NT];
@@ -800,7 +801,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
         bs0[n] = PREC == PSPLIT ? colsc[p0][lc * NTL + n] : 0;
         bs1[n] = PREC == PSPLIT ? colsc[p1][lc * NTL + n] : 0;
       }
-      constexpr int PF = kPrefetch / 2;
+      constexpr int PF = PIN ? kPrefetch / 2 : kPrefetch / 4;
       const int nsteps = (ih + 3) >> 2;
       AFrag<PREC> ac0[PF], an0[PF], ac1[PF], an1[PF];
       auto fetch = [&](int s0) {
@@ -1076,9 +1077,10 @@ __device__ void run_item(const BatchItem& it, const BatchGroupDev& g, double* ld
       // work-group's LDS for the largest pair of output blocks of any group
       level_trans_body<NT, PREC, false, false>(g.tasks[it.task], it.blk, g.fp, g.idx, g.pairs, in, out, g.R, g.io,
                                         lds);
-    } else {  // transposed finals always take 16-column blocks
-      final_trans_body<16, 128, PREC, false>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0, g.v1,
-                                      g.l, g.R, lds);
+    } else {  // transposed finals always take 16-column blocks, and keep two output tiles per
+              // wave and pass (the persistent loop's state leaves no registers for six)
+      final_trans_body<16, 128, PREC, false, 2>(g.finals[it.task], it.blk, g.fp, g.y, g.rowscale, g.half, g.v0,
+                                                g.v1, g.l, g.R, lds);
     }
   }
 }
