@@ -115,16 +115,21 @@ template <> struct BFrag<P64> { double b; };
 template <> struct BFrag<PSPLIT> { float b1, b2; };
 template <> struct BFrag<P32> { float b; };
 
-// sh = kSliceBits - e for the column's max |x| < 2^e (0 for an all-zero column); the
-// leading slice is x1 = 2^-sh rint(2^sh x), exact (ldexp, so no scale can overflow).
+// sh = kSliceBits - e for the column's max |x| < 2^e (0 for an all-zero column).  The split
+// form works in units of the column's grid 2^-sh: the leading slice is the integer
+// x1 = rint(2^sh x) (|x1| <= 2^11, exact in FP32) and the remainder x2 = fp32(2^sh x - x1)
+// (|x2| <= 1/2), so both stay normal FP32 numbers whatever the column's magnitude; the
+// accumulators hold results in the same units and are scaled back when read (ldexp: exact,
+// no scale can overflow).
 template <int PREC>
 __device__ __forceinline__ BFrag<PREC> make_b(double x, int sh);
 template <>
 __device__ __forceinline__ BFrag<P64> make_b<P64>(double x, int) { return {x}; }
 template <>
 __device__ __forceinline__ BFrag<PSPLIT> make_b<PSPLIT>(double x, int sh) {
-  const double x1 = ldexp(rint(ldexp(x, sh)), -sh);
-  return {static_cast<float>(x1), static_cast<float>(x - x1)};
+  const double y = ldexp(x, sh);
+  const double y1 = rint(y);
+  return {static_cast<float>(y1), static_cast<float>(y - y1)};
 }
 template <>
 __device__ __forceinline__ BFrag<P32> make_b<P32>(double x, int) { return {static_cast<float>(x)}; }
@@ -192,11 +197,12 @@ template <>
 struct Acc<P64> {
   d4 v;
   __device__ void zero() { v = d4{0.0, 0.0, 0.0, 0.0}; }
-  __device__ void set(int e, double x) { v[e] = x; }
+  __device__ void set(int e, double x, int) { v[e] = x; }
   __device__ void step(const AFrag<P64>& a, const BFrag<P64>& b) { v = mfma64(a.a, b.b, v); }
   __device__ void flush_step() {}
   __device__ void flush() {}
-  __device__ double get(int e) const { return v[e]; }
+  __device__ double get(int e, int) const { return v[e]; }
+  __device__ void rescale(int) {}
 };
 template <>
 struct Acc<PSPLIT> {
@@ -207,7 +213,8 @@ struct Acc<PSPLIT> {
     ex = f4{0.f, 0.f, 0.f, 0.f};
     cr = ex;
   }
-  __device__ void set(int e, double x) { hi[e] = x; }
+  // sh: the shift of the lane's column (values held in units of 2^-sh, see make_b)
+  __device__ void set(int e, double x, int sh) { hi[e] = ldexp(x, sh); }
   // one K-step (flushed after every K-step): the exact leading sum of four products, then
   // the corrections, smallest first
   __device__ void step(const AFrag<PSPLIT>& a, const BFrag<PSPLIT>& b) {
@@ -223,8 +230,13 @@ struct Acc<PSPLIT> {
     cr = ex;
   }
   __device__ void flush() {}
-  __device__ double get(int e) const {
-    return hi[e] + static_cast<double>(ex[e]) + static_cast<double>(cr[e]);
+  __device__ double get(int e, int sh) const {
+    return ldexp(hi[e] + static_cast<double>(ex[e]) + static_cast<double>(cr[e]), -sh);
+  }
+  // the column's grid moves from 2^-sh to 2^-(sh + d) (after a flush)
+  __device__ void rescale(int d) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hi[e] = ldexp(hi[e], d);
   }
 };
 template <>
@@ -235,11 +247,12 @@ struct Acc<P32> {
     base = d4{0.0, 0.0, 0.0, 0.0};
     v = f4{0.f, 0.f, 0.f, 0.f};
   }
-  __device__ void set(int e, double x) { base[e] = x; }
+  __device__ void set(int e, double x, int) { base[e] = x; }
   __device__ void step(const AFrag<P32>& a, const BFrag<P32>& b) { v = mfma32(a.a1 + a.a2, b.b, v); }
   __device__ void flush_step() {}
   __device__ void flush() {}
-  __device__ double get(int e) const { return base[e] + static_cast<double>(v[e]); }
+  __device__ double get(int e, int) const { return base[e] + static_cast<double>(v[e]); }
+  __device__ void rescale(int) {}
 };
 
 // Per-column slice shifts of a rows x NT block: sh[c] = kSliceBits - e, max |x| < 2^e.
@@ -318,7 +331,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
-          acc[u][n].set(v, row < k ? xs[skel[row] * LD + lc * NTL + n] : 0.0);
+          acc[u][n].set(v, row < k ? xs[skel[row] * LD + lc * NTL + n] : 0.0, bsc[n]);
         }
       }
     }
@@ -391,7 +404,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const int row = (mt0 + u) * 16 + drow<PREC>(v, lr);
         if (row < k) {
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n] = acc[u][n].get(v);
+          for (int n = 0; n < NTL; ++n) ob[static_cast<long long>(row) * R + n] = acc[u][n].get(v, bsc[n]);
         }
       }
     }
@@ -550,7 +563,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         if (j < nr) {
           double* dst = acc_l + static_cast<int>(red[j]) * LD + lc * NTL;
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) atomicAdd(dst + n, acc[u][n].get(v));
+          for (int n = 0; n < NTL; ++n) atomicAdd(dst + n, acc[u][n].get(v, bsc[n]));
         }
       }
     }
@@ -702,7 +715,7 @@ __device__ void final_synth_body(const FinalTask& ft, int blk, const FacPtr& fp,
         double* ym = Y + y_row(l, ft.m, l - 1 - row) * R + c0 + lc * NTL;
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
-          const double e = E[n].get(v), od = O[n].get(v);
+          const double e = E[n].get(v, bsc[0][n]), od = O[n].get(v, bsc[1][n]);
           yp[n] = (e + od) * s;
           ym[n] = (e - od) * s;
         }
@@ -757,6 +770,8 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   for (int u = 0; u < MAXT; ++u)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[u][n].zero();
+  // split form: each row chunk has its own column grids; the sums so far move to the new grid
+  int shp[2][NTL] = {};
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     __syncthreads();
@@ -780,6 +795,16 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       cut_block<NT, LD>(eo[0], ih, colsc[0]);
       cut_block<NT, LD>(eo[1], ih, colsc[1]);
       __syncthreads();
+#pragma unroll
+      for (int u = 0; u < MAXT; ++u) {
+        const int pu = t0 + wave + 4 * u < nm0 ? 0 : 1;
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) acc[u][n].rescale(colsc[pu][lc * NTL + n] - shp[pu][n]);
+      }
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) shp[pp][n] = colsc[pp][lc * NTL + n];
     }
     // Two output tiles per pass through the rows, so that one tile's matrix instructions
     // overlap the other's accumulator hand-over (the split form flushes after every K-step);
@@ -859,7 +884,8 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       const int a = mt * 16 + drow<PREC>(v, lr);
       if (a < k) {
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) vout[static_cast<long long>(a) * R + n] = acc[u][n].get(v);
+        for (int n = 0; n < NTL; ++n)
+          vout[static_cast<long long>(a) * R + n] = acc[u][n].get(v, PREC == PSPLIT ? colsc[p][lc * NTL + n] : 0);
       }
     }
   }

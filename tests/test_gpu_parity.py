@@ -301,6 +301,30 @@ def test_split_precision_real_fields_and_adjoint():
     assert _rel(adj, oracle.synth_adjoint(r, l, kind="real")).max() < SPLIT_TOL
 
 
+_MAG_CASE = {}
+
+
+@pytest.mark.parametrize("scale", [1e-60, 1e-20, 1e20, 1e60])
+def test_split_precision_any_magnitude(scale):
+    # the split slices of the vectors live on their columns' grids as integers plus a bounded
+    # FP32 remainder, so fields far outside FP32's range transform as well as unit ones (the
+    # oracle's map is linear: its output for the scaled input is the scaled output); l = 256
+    # with C = 64 gives final blocks of more than 128 rows, which the analysis takes in two
+    # chunks with grids of their own
+    l, C, F = 256, 64, 4
+    P = _plan(l, C, eps=1e-12)
+    if not _MAG_CASE:
+        beta = syn.coefficients(l, F, seed=5, power=1.5)
+        grid = syn.grid(l, F, seed=6)
+        _MAG_CASE.update(beta=beta, grid=grid, ref_s=oracle.synth(beta, l), ref_a=oracle.analyze(grid, l))
+    beta, grid, ref_s, ref_a = (_MAG_CASE[k] for k in ("beta", "grid", "ref_s", "ref_a"))
+    got_s = P.synth(_dev(beta * scale), precision="split32").cpu().numpy() / scale
+    got_a = P.analyze(_dev(grid * scale), precision="split32").cpu().numpy() / scale
+    es, ea = _rel(got_s, ref_s).max(), _rel(got_a, ref_a).max()
+    print(f"split at scale {scale:g}: synthesis {es:.2e}, analysis {ea:.2e}", flush=True)
+    assert es < SPLIT_TOL and ea < SPLIT_TOL
+
+
 def test_split_precision_needs_matrix_core_widths():
     from paper_0910_5435_amd import _lib
 
