@@ -2,7 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -117,6 +122,98 @@ class DeviceScope {
   bool switched_ = false;
   bool ok_ = true;
 };
+
+}  // namespace
+
+// ------------------------------------------------------------ allocation and call tracing
+
+namespace sht {
+
+namespace {
+// allocations left before the injected failures begin; -1: no injection
+std::atomic<long long> g_alloc_left{-1};
+
+bool alloc_refused() {
+  long long v = g_alloc_left.load(std::memory_order_relaxed);
+  while (v > 0 && !g_alloc_left.compare_exchange_weak(v, v - 1, std::memory_order_relaxed)) {
+  }
+  return v == 0;
+}
+
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  if (alloc_refused()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_alloc(void** p, size_t bytes) {
+  if (alloc_refused()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes);
+}
+
+AllocFaultScope::AllocFaultScope() {
+  const char* e = std::getenv("SHT_TEST_FAIL_ALLOC_AFTER");
+  const long long n = e && *e ? std::atoll(e) : -1;
+  g_alloc_left.store(n < 0 ? -1 : n, std::memory_order_relaxed);
+}
+
+AllocFaultScope::~AllocFaultScope() { g_alloc_left.store(-1, std::memory_order_relaxed); }
+
+TraceCall::TraceCall(const char* name, int device, void* stream) : name_(name), device_(device), stream_(stream) {
+  const char* e = std::getenv("SHT_TRACE");
+  level_ = e && *e ? std::atoi(e) : 0;
+  if (level_ <= 0) return;
+  t0_ = wall_ms();
+  if (level_ >= 2 && device_ >= 0) {
+    DeviceScope ds(device_);
+    if (ds.ok() && hipEventCreate(&ev_[0]) == hipSuccess && hipEventCreate(&ev_[1]) == hipSuccess)
+      (void)hipEventRecord(ev_[0], static_cast<hipStream_t>(stream_));
+  }
+}
+
+TraceCall::~TraceCall() {
+  if (!ev_[0] && !ev_[1]) return;
+  DeviceScope ds(device_);
+  for (hipEvent_t& e : ev_)
+    if (e) (void)hipEventDestroy(e);
+}
+
+void TraceCall::args(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(args_, sizeof(args_), fmt, ap);
+  va_end(ap);
+}
+
+int TraceCall::done(int rc) {
+  if (level_ <= 0) return rc;
+  const double host_ms = wall_ms() - t0_;
+  char dev[48] = "";
+  if (ev_[0] && ev_[1]) {
+    DeviceScope ds(device_);
+    float ms = 0.0f;
+    if (hipEventRecord(ev_[1], static_cast<hipStream_t>(stream_)) == hipSuccess &&
+        hipEventSynchronize(ev_[1]) == hipSuccess && hipEventElapsedTime(&ms, ev_[0], ev_[1]) == hipSuccess)
+      std::snprintf(dev, sizeof(dev), ", device %.3f ms", static_cast<double>(ms));
+  }
+  std::fprintf(stderr, "sht: %s(%s) -> %d (%s), host %.3f ms%s\n", name_, args_, rc, sht_strerror(rc), host_ms,
+               dev);
+  return rc;
+}
+
+}  // namespace sht
+
+namespace {
 
 int check_call(const sht_plan_s* P, int precision, const void* a, const void* b, int F, void* ws,
                size_t wsb) {
@@ -343,6 +440,7 @@ int make_plan(int l, double eps, const sht_plan_opts& o, bool maps, sht_plan_t* 
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return SHT_EHIP;
   DeviceScope ds(dev);
   if (!ds.ok()) return SHT_EHIP;
+  AllocFaultScope faults;
   sht_plan_s* P = new (std::nothrow) sht_plan_s();
   if (!P) return SHT_ENOMEM;
   P->l = l;
@@ -362,10 +460,10 @@ int make_plan(int l, double eps, const sht_plan_opts& o, bool maps, sht_plan_t* 
   }
   // a plan built for a split, FP32 or int8 default derives those factor copies now, so that
   // its transforms never allocate or wait
-  if (rc == SHT_OK && (P->precision == SHT_SPLIT32 || P->precision == SHT_FP32) &&
-      split_factors(P, nullptr) != hipSuccess)
-    rc = SHT_EHIP;
-  if (rc == SHT_OK && P->precision == SHT_INT8 && i8_prepare(P, nullptr) != hipSuccess) rc = SHT_EHIP;
+  if (rc == SHT_OK && P->precision != SHT_FP64) {
+    const hipError_t e = P->precision == SHT_INT8 ? i8_prepare(P, nullptr) : split_factors(P, nullptr);
+    if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
+  }
   if (rc == SHT_OK && o.split_only) {
     (void)hipFree(P->d.fac);
     (void)hipFree(P->d.fac_t);
@@ -383,7 +481,7 @@ int make_plan(int l, double eps, const sht_plan_opts& o, bool maps, sht_plan_t* 
 
 }  // namespace
 
-int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+static int plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
   sht_plan_opts o;
@@ -399,7 +497,15 @@ int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   return make_plan(l, eps, o, false, out);
 }
 
-int sht_order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+int sht_plan_ex(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+  TraceCall tc("sht_plan_ex", -1, nullptr);
+  if (tc.on())
+    tc.args("l=%d, eps=%g, leaf_width=%d, precision=%d, id_device=%d", l, eps, opts ? opts->leaf_width : 0,
+            opts ? opts->precision : SHT_FP64, opts ? opts->id_device : 0);
+  return tc.done(plan_ex(l, eps, opts, out));
+}
+
+static int order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
   sht_plan_opts o;
@@ -410,6 +516,12 @@ int sht_order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out
   if (o.precision < SHT_FP64 || o.precision > SHT_INT8) return SHT_EINVAL;
   if (l > 2048 || o.precision != SHT_FP64 || o.split_only || o.cache_dir || o.id_device) return SHT_EUNSUPPORTED;
   return make_plan(l, eps, o, true, out);
+}
+
+int sht_order_plan(int l, double eps, const sht_plan_opts* opts, sht_plan_t* out) {
+  TraceCall tc("sht_order_plan", -1, nullptr);
+  if (tc.on()) tc.args("l=%d, eps=%g, leaf_width=%d", l, eps, opts ? opts->leaf_width : 0);
+  return tc.done(order_plan(l, eps, opts, out));
 }
 
 long long sht_order_rows(sht_plan_t plan) {
@@ -429,8 +541,8 @@ size_t sht_order_workspace_bytes(sht_plan_t plan, int R) {
   return 2 * align256(static_cast<size_t>(plan->rows_v) * R * 8);
 }
 
-int sht_order_apply(sht_plan_t plan, const double* in, double* out, int R, int transpose, void* ws, size_t wsb,
-                    void* stream) {
+static int order_apply(sht_plan_t plan, const double* in, double* out, int R, int transpose, void* ws, size_t wsb,
+                       void* stream) {
   sht_plan_s* P = plan;
   if (!P || !P->maps || !in || !out || !ws || R < 1 || R > 65535 || (transpose != 0 && transpose != 1))
     return SHT_EINVAL;
@@ -470,7 +582,14 @@ int sht_order_apply(sht_plan_t plan, const double* in, double* out, int R, int t
   return SHT_OK;
 }
 
-int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
+int sht_order_apply(sht_plan_t plan, const double* in, double* out, int R, int transpose, void* ws, size_t wsb,
+                    void* stream) {
+  TraceCall tc("sht_order_apply", plan ? plan->device : -1, stream);
+  if (tc.on()) tc.args("l=%d, R=%d, transpose=%d", plan ? plan->l : 0, R, transpose);
+  return tc.done(order_apply(plan, in, out, R, transpose, ws, wsb, stream));
+}
+
+static int plan_prepare(sht_plan_t plan, int precision, void* stream) {
   if (!plan) return SHT_EINVAL;
   if (precision < SHT_FP64 || precision > SHT_INT8) return SHT_EINVAL;
   if (plan->maps && precision != SHT_FP64) return SHT_EUNSUPPORTED;
@@ -482,6 +601,7 @@ int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
   hipError_t e;
   {
     std::lock_guard<std::mutex> lock(plan->split_mu);
+    AllocFaultScope faults;
     e = precision == SHT_INT8 ? i8_prepare(plan, static_cast<hipStream_t>(stream))
                               : split_factors(plan, static_cast<hipStream_t>(stream));
   }
@@ -489,7 +609,16 @@ int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
   return e == hipSuccess ? SHT_OK : SHT_EHIP;
 }
 
+int sht_plan_prepare(sht_plan_t plan, int precision, void* stream) {
+  TraceCall tc("sht_plan_prepare", plan ? plan->device : -1, stream);
+  if (tc.on()) tc.args("l=%d, precision=%d", plan ? plan->l : 0, precision);
+  return tc.done(plan_prepare(plan, precision, stream));
+}
+
 void sht_destroy(sht_plan_t plan) {
+  TraceCall tc("sht_destroy", -1, nullptr);
+  if (tc.on()) tc.args("l=%d", plan ? plan->l : 0);
+  tc.done(SHT_OK);
   if (!plan) return;
   DeviceScope ds(plan->device);
   plan->prof.clear();
@@ -502,31 +631,42 @@ size_t sht_workspace_bytes(sht_plan_t plan, int nfields, int precision) {
   return ws_bytes(plan, nfields);
 }
 
+namespace {
+// One traced transform call: op 0 synthesis, 1 analysis, 2 adjoint of synthesis.
+int traced_transform(const char* name, sht_plan_t plan, int prec, const double* in, double* out, int F, void* ws,
+                     size_t wsb, void* stream, int op) {
+  TraceCall tc(name, plan ? plan->device : -1, stream);
+  if (tc.on()) tc.args("l=%d, F=%d, precision=%d", plan ? plan->l : 0, F, prec);
+  if (!plan) return tc.done(SHT_EINVAL);
+  if (op == 0) return tc.done(run_synth(plan, prec, in, out, F, ws, wsb, stream, true));
+  return tc.done(run_transposed(plan, prec, in, out, F, ws, wsb, stream, op == 2));
+}
+}  // namespace
+
 int sht_synth(sht_plan_t plan, const double* coeff, double* grid, int F, void* ws, size_t wsb,
               void* stream) {
-  return plan ? run_synth(plan, plan->precision, coeff, grid, F, ws, wsb, stream, true) : SHT_EINVAL;
+  return traced_transform("sht_synth", plan, plan ? plan->precision : SHT_FP64, coeff, grid, F, ws, wsb, stream, 0);
 }
 int sht_analyze(sht_plan_t plan, const double* grid, double* coeff, int F, void* ws, size_t wsb,
                 void* stream) {
-  return plan ? run_transposed(plan, plan->precision, grid, coeff, F, ws, wsb, stream, false)
-              : SHT_EINVAL;
+  return traced_transform("sht_analyze", plan, plan ? plan->precision : SHT_FP64, grid, coeff, F, ws, wsb, stream, 1);
 }
 int sht_synth_adjoint(sht_plan_t plan, const double* grid_cot, double* coeff_cot, int F, void* ws,
                       size_t wsb, void* stream) {
-  return plan ? run_transposed(plan, plan->precision, grid_cot, coeff_cot, F, ws, wsb, stream, true)
-              : SHT_EINVAL;
+  return traced_transform("sht_synth_adjoint", plan, plan ? plan->precision : SHT_FP64, grid_cot, coeff_cot, F, ws,
+                          wsb, stream, 2);
 }
 int sht_synth_ex(sht_plan_t plan, int prec, const double* coeff, double* grid, int F, void* ws,
                  size_t wsb, void* stream) {
-  return run_synth(plan, prec, coeff, grid, F, ws, wsb, stream, true);
+  return traced_transform("sht_synth_ex", plan, prec, coeff, grid, F, ws, wsb, stream, 0);
 }
 int sht_analyze_ex(sht_plan_t plan, int prec, const double* grid, double* coeff, int F, void* ws,
                    size_t wsb, void* stream) {
-  return run_transposed(plan, prec, grid, coeff, F, ws, wsb, stream, false);
+  return traced_transform("sht_analyze_ex", plan, prec, grid, coeff, F, ws, wsb, stream, 1);
 }
 int sht_synth_adjoint_ex(sht_plan_t plan, int prec, const double* grid_cot, double* coeff_cot, int F,
                          void* ws, size_t wsb, void* stream) {
-  return run_transposed(plan, prec, grid_cot, coeff_cot, F, ws, wsb, stream, true);
+  return traced_transform("sht_synth_adjoint_ex", plan, prec, grid_cot, coeff_cot, F, ws, wsb, stream, 2);
 }
 
 int sht_plan_stats(sht_plan_t plan, sht_stats* out) {
@@ -622,10 +762,10 @@ int sht_plan_columns(sht_plan_t plan, int m, int p, double* q, int ldq) {
     if (e != hipSuccess && rc == SHT_OK) rc = SHT_EHIP;
     return rc == SHT_OK;
   };
-  if (ok(hipMalloc(&dm, 4)) && ok(hipMalloc(&dp, 4)) && ok(hipMalloc(&dn, 4)) &&
-      ok(hipMalloc(&dprev, 16 * l)) && ok(hipMalloc(&dcur, 16 * l)) && ok(hipMalloc(&dexp, 4 * l)) &&
-      ok(hipMalloc(&dout, 8 * static_cast<size_t>(C) * l)) && ok(hipMalloc(&dx, 8 * l)) &&
-      ok(hipMalloc(&dsw, 8 * l)) && ok(hipMemcpy(dm, &m, 4, hipMemcpyHostToDevice)) &&
+  if (ok(dev_alloc(&dm, 4)) && ok(dev_alloc(&dp, 4)) && ok(dev_alloc(&dn, 4)) &&
+      ok(dev_alloc(&dprev, 16 * l)) && ok(dev_alloc(&dcur, 16 * l)) && ok(dev_alloc(&dexp, 4 * l)) &&
+      ok(dev_alloc(&dout, 8 * static_cast<size_t>(C) * l)) && ok(dev_alloc(&dx, 8 * l)) &&
+      ok(dev_alloc(&dsw, 8 * l)) && ok(hipMemcpy(dm, &m, 4, hipMemcpyHostToDevice)) &&
       ok(hipMemcpy(dp, &p, 4, hipMemcpyHostToDevice)) &&
       ok(hipMemcpy(dn, &n, 4, hipMemcpyHostToDevice)) &&
       ok(hipMemcpy(dx, plan->xp.data(), 8 * l, hipMemcpyHostToDevice)) &&
@@ -683,10 +823,10 @@ int sht_dense_q(sht_plan_t plan, int mp0, int count, double* q, long long stride
     return rc == SHT_OK;
   };
   const size_t nc = static_cast<size_t>(count);
-  if (ok(hipMalloc(&dm, 4 * nc)) && ok(hipMalloc(&dp, 4 * nc)) && ok(hipMalloc(&dn, 4 * nc)) &&
-      ok(hipMalloc(&dprev, 16 * nc * l)) && ok(hipMalloc(&dcur, 16 * nc * l)) &&
-      ok(hipMalloc(&dexp, 4 * nc * l)) && ok(hipMalloc(&dout, 8 * nc * C * l)) &&
-      ok(hipMalloc(&dx, 8 * static_cast<size_t>(l))) && ok(hipMalloc(&dsw, 8 * static_cast<size_t>(l))) &&
+  if (ok(dev_alloc(&dm, 4 * nc)) && ok(dev_alloc(&dp, 4 * nc)) && ok(dev_alloc(&dn, 4 * nc)) &&
+      ok(dev_alloc(&dprev, 16 * nc * l)) && ok(dev_alloc(&dcur, 16 * nc * l)) &&
+      ok(dev_alloc(&dexp, 4 * nc * l)) && ok(dev_alloc(&dout, 8 * nc * C * l)) &&
+      ok(dev_alloc(&dx, 8 * static_cast<size_t>(l))) && ok(dev_alloc(&dsw, 8 * static_cast<size_t>(l))) &&
       ok(hipMemcpy(dm, hm.data(), 4 * nc, hipMemcpyHostToDevice)) &&
       ok(hipMemcpy(dp, hp.data(), 4 * nc, hipMemcpyHostToDevice)) &&
       ok(hipMemcpy(dn, hn.data(), 4 * nc, hipMemcpyHostToDevice)) &&

@@ -729,8 +729,8 @@ hipError_t i8_prepare(sht_plan_s* P, hipStream_t s) {
   if (P->final_maxh > 4096) return hipErrorInvalidValue;
   int8_t* dig = nullptr;
   int16_t* dex = nullptr;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&dig), std::max<long long>(P->n_dig, 1024));
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&dex), std::max<long long>(P->n_dex, 16) * sizeof(int16_t));
+  hipError_t e = dev_alloc(reinterpret_cast<void**>(&dig), std::max<long long>(P->n_dig, 1024));
+  if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void**>(&dex), std::max<long long>(P->n_dex, 16) * sizeof(int16_t));
   for (long long b0 = 0; e == hipSuccess && b0 < P->n_blocks; b0 += 1 << 20) {
     const long long nb = std::min<long long>(1 << 20, P->n_blocks - b0);
     hipLaunchKernelGGL(k_i8_prep, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, P->d.fac, P->d.i8blocks + b0,

@@ -1185,7 +1185,7 @@ hipError_t split_factors(sht_plan_s* P, hipStream_t s) {
   const size_t n = static_cast<size_t>(std::max<long long>(P->n_fac, 4));
   float2* bufs[2] = {nullptr, nullptr};
   for (int b = 0; b < 2; ++b) {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&bufs[b]), n * sizeof(float2));
+    hipError_t e = dev_alloc(reinterpret_cast<void**>(&bufs[b]), n * sizeof(float2));
     if (e != hipSuccess) {
       if (b) (void)hipFree(bufs[0]);
       return e;

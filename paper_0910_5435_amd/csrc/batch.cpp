@@ -232,9 +232,9 @@ int build_set(sht_batch_s* B, int si, int nt, int nq, SetDev& out, std::vector<B
   out.nphase = nphase;
   out.nitems = static_cast<long long>(items.size());
   out.lds = lds;
-  if (hipMalloc(reinterpret_cast<void**>(&out.groups), gdev.size() * sizeof(BatchGroupDev)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&out.items), std::max<size_t>(1, items.size()) * sizeof(BatchItem)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&out.qoff), qoff.size() * sizeof(int)) != hipSuccess)
+  if (dev_alloc(reinterpret_cast<void**>(&out.groups), gdev.size() * sizeof(BatchGroupDev)) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&out.items), std::max<size_t>(1, items.size()) * sizeof(BatchItem)) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&out.qoff), qoff.size() * sizeof(int)) != hipSuccess)
     return SHT_ENOMEM;
   if (hipMemcpy(out.groups, gdev.data(), gdev.size() * sizeof(BatchGroupDev), hipMemcpyHostToDevice) != hipSuccess ||
       (!items.empty() &&
@@ -284,7 +284,7 @@ int configure(sht_batch_s* B, const sht_batch_config& c) {
       return SHT_EHIP;
     }
   B->n_sync = nsync;
-  if (hipMalloc(reinterpret_cast<void**>(&B->d_sync), static_cast<size_t>(nsync + 1) * sizeof(unsigned)) != hipSuccess) {
+  if (dev_alloc(reinterpret_cast<void**>(&B->d_sync), static_cast<size_t>(nsync + 1) * sizeof(unsigned)) != hipSuccess) {
     free_lists(B);
     return SHT_ENOMEM;
   }
@@ -341,10 +341,9 @@ int configure(sht_batch_s* B, const sht_batch_config& c) {
 
 }  // namespace
 
-extern "C" {
-
-int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, size_t workspace_limit,
-                     void* stream, sht_batch_t* out) {
+namespace {
+int batch_create(const sht_request* reqs, int nreq, int op, int precision, size_t workspace_limit, void* stream,
+                 sht_batch_t* out) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
   if (!reqs || nreq < 1) return SHT_EINVAL;
@@ -441,8 +440,8 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
     for (size_t u : used) B->ws_bytes = std::max(B->ws_bytes, u);
     for (std::vector<int>& m : B->sets) std::sort(m.begin(), m.end());
   }
-  if (rc == SHT_OK && (hipMalloc(reinterpret_cast<void**>(&B->ws), std::max<size_t>(B->ws_bytes, 256)) != hipSuccess ||
-                       hipMalloc(reinterpret_cast<void**>(&B->d_status), sizeof(int)) != hipSuccess))
+  if (rc == SHT_OK && (dev_alloc(reinterpret_cast<void**>(&B->ws), std::max<size_t>(B->ws_bytes, 256)) != hipSuccess ||
+                       dev_alloc(reinterpret_cast<void**>(&B->d_status), sizeof(int)) != hipSuccess))
     rc = SHT_ENOMEM;
   // the Y rows of padding columns are never written by the transposed FFT: clear them once
   if (rc == SHT_OK && hipMemset(B->ws, 0, B->ws_bytes) != hipSuccess) rc = SHT_EHIP;
@@ -455,8 +454,8 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
       tin[f] = const_cast<double*>(static_cast<const double*>(g.in[f]));
       tout[f] = static_cast<double*>(g.out[f]);
     }
-    if (hipMalloc(reinterpret_cast<void**>(&g.d_in), n * sizeof(double*)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&g.d_out), n * sizeof(double*)) != hipSuccess) {
+    if (dev_alloc(reinterpret_cast<void**>(&g.d_in), n * sizeof(double*)) != hipSuccess ||
+        dev_alloc(reinterpret_cast<void**>(&g.d_out), n * sizeof(double*)) != hipSuccess) {
       rc = SHT_ENOMEM;
       break;
     }
@@ -493,6 +492,18 @@ int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, s
   return SHT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int sht_batch_create(const sht_request* reqs, int nreq, int op, int precision, size_t workspace_limit,
+                     void* stream, sht_batch_t* out) {
+  TraceCall tc("sht_batch_create", reqs && nreq > 0 && reqs[0].plan ? reqs[0].plan->device : -1, nullptr);
+  if (tc.on()) tc.args("nreq=%d, op=%d, precision=%d", nreq, op, precision);
+  AllocFaultScope faults;
+  return tc.done(batch_create(reqs, nreq, op, precision, workspace_limit, stream, out));
+}
+
 int sht_batch_configure(sht_batch_t B, const sht_batch_config* cfg) {
   if (!B || !cfg) return SHT_EINVAL;
   sht_batch_config c = B->cfg;
@@ -510,8 +521,9 @@ int sht_batch_configure(sht_batch_t B, const sht_batch_config* cfg) {
 }
 
 int sht_batch_run(sht_batch_t B, void* stream) {
-  if (!B || !B->exec) return SHT_EINVAL;
-  return hipGraphLaunch(B->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? SHT_OK : SHT_EHIP;
+  TraceCall tc("sht_batch_run", B ? B->device : -1, stream);
+  if (!B || !B->exec) return tc.done(SHT_EINVAL);
+  return tc.done(hipGraphLaunch(B->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? SHT_OK : SHT_EHIP);
 }
 
 int sht_batch_check(sht_batch_t B, void* stream) {

@@ -389,7 +389,7 @@ struct Grow {
     if (p) (void)hipFree(p);
     p = nullptr;
     cap = 0;
-    const hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    const hipError_t e = dev_alloc(&p, std::max<size_t>(bytes, 256));
     if (e == hipSuccess) cap = bytes;
     return e;
   }
@@ -428,7 +428,7 @@ struct Pinned {
     if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
-    const hipError_t e = hipHostMalloc(&p, std::max<size_t>(bytes, 256));
+    const hipError_t e = pinned_alloc(&p, std::max<size_t>(bytes, 256));
     if (e == hipSuccess) cap = bytes;
     return e;
   }

@@ -70,7 +70,7 @@ class FactorStream {
   FactorStream(double* dev, size_t total) : dev_(dev), total_(total) {
     for (int b = 0; b < 2; ++b) {
       if (err_ == hipSuccess)
-        err_ = hipHostMalloc(reinterpret_cast<void**>(&stage_[b]), kCap * sizeof(double));
+        err_ = pinned_alloc(reinterpret_cast<void**>(&stage_[b]), kCap * sizeof(double));
       if (err_ == hipSuccess) err_ = hipEventCreateWithFlags(&ev_[b], hipEventDisableTiming);
     }
   }
@@ -139,10 +139,10 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o);
 int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees);
 void free_plan_device(sht_plan_s* P);
 
-#define HIP_TRY(expr)                         \
-  do {                                        \
-    hipError_t _e = (expr);                   \
-    if (_e != hipSuccess) return SHT_EHIP;    \
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess) return _e == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP; \
   } while (0)
 
 int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
@@ -252,21 +252,21 @@ int build_plan(sht_plan_s* P, const sht_plan_opts& o) {
   batch = std::max(2, batch - (batch % 2));
 
   DevBuf dx, dsw, dm, dp, dn, dprev, dcur, dexp, dout;
-  HIP_TRY(hipMalloc(&dx.p, sizeof(double) * l));
-  HIP_TRY(hipMalloc(&dsw.p, sizeof(double) * l));
+  HIP_TRY(dev_alloc(&dx.p, sizeof(double) * l));
+  HIP_TRY(dev_alloc(&dsw.p, sizeof(double) * l));
   std::vector<double> sw(l);
   for (int i = 0; i < l; ++i) sw[i] = std::sqrt(2.0 * P->wp[i]);
   HIP_TRY(hipMemcpy(dx.p, P->xp.data(), sizeof(double) * l, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(dsw.p, sw.data(), sizeof(double) * l, hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc(&dm.p, sizeof(int) * batch));
-  HIP_TRY(hipMalloc(&dp.p, sizeof(int) * batch));
-  HIP_TRY(hipMalloc(&dn.p, sizeof(int) * batch));
-  HIP_TRY(hipMalloc(&dprev.p, 2 * sizeof(double) * batch * l));  // double-double state
-  HIP_TRY(hipMalloc(&dcur.p, 2 * sizeof(double) * batch * l));
-  HIP_TRY(hipMalloc(&dexp.p, sizeof(int) * batch * l));
-  HIP_TRY(hipMalloc(&dout.p, sizeof(double) * batch * chunk_doubles));
+  HIP_TRY(dev_alloc(&dm.p, sizeof(int) * batch));
+  HIP_TRY(dev_alloc(&dp.p, sizeof(int) * batch));
+  HIP_TRY(dev_alloc(&dn.p, sizeof(int) * batch));
+  HIP_TRY(dev_alloc(&dprev.p, 2 * sizeof(double) * batch * l));  // double-double state
+  HIP_TRY(dev_alloc(&dcur.p, 2 * sizeof(double) * batch * l));
+  HIP_TRY(dev_alloc(&dexp.p, sizeof(int) * batch * l));
+  HIP_TRY(dev_alloc(&dout.p, sizeof(double) * batch * chunk_doubles));
   double* host_chunk = nullptr;
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&host_chunk), sizeof(double) * batch * chunk_doubles));
+  HIP_TRY(pinned_alloc(reinterpret_cast<void**>(&host_chunk), sizeof(double) * batch * chunk_doubles));
   std::unique_ptr<double, void (*)(double*)> host_guard(host_chunk,
                                                           [](double* q) { (void)hipHostFree(q); });
 
@@ -411,7 +411,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   size_t n_fac_total = 0;
   for (const BfTree& T : trees) n_fac_total += static_cast<size_t>(T.factor_entries);
   {
-    const hipError_t ea = hipMalloc(reinterpret_cast<void**>(&P->d.fac),
+    const hipError_t ea = dev_alloc(reinterpret_cast<void**>(&P->d.fac),
                                     std::max<size_t>(n_fac_total, 2) * sizeof(double));
     if (ea != hipSuccess) return ea == hipErrorOutOfMemory ? SHT_ENOMEM : SHT_EHIP;
   }
@@ -673,7 +673,7 @@ int pack_plan(sht_plan_s* P, std::vector<BfTree>& trees) {
   // device upload
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(dst, bytes);
+    hipError_t e = dev_alloc(dst, bytes);
     if (e != hipSuccess) return e;
     if (src) return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     return hipSuccess;

@@ -364,4 +364,50 @@ class BfTree;
 int build_trees_on_device(sht_plan_s* P, std::vector<BfTree>& trees, int first_pair, CacheAppend append,
                           double& t_cols, double& t_comp);
 
+// ------------------------------------------------------------ allocation and call tracing
+// Every device and pinned-host allocation of the library goes through dev_alloc /
+// pinned_alloc.  Error-path tests: while an AllocFaultScope is alive (the entry points that
+// build plans, factor copies and batches open one), SHT_TEST_FAIL_ALLOC_AFTER = n in the
+// environment lets the first n allocations through and fails every later one with
+// hipErrorOutOfMemory without touching the device.  Unset or negative: no failures.  Meant
+// for one thread at a time.
+hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t pinned_alloc(void** p, size_t bytes);
+template <class T>
+hipError_t dev_alloc(T** p, size_t bytes) {
+  return dev_alloc(reinterpret_cast<void**>(p), bytes);
+}
+template <class T>
+hipError_t pinned_alloc(T** p, size_t bytes) {
+  return pinned_alloc(reinterpret_cast<void**>(p), bytes);
+}
+struct AllocFaultScope {
+  AllocFaultScope();
+  ~AllocFaultScope();
+  AllocFaultScope(const AllocFaultScope&) = delete;
+  AllocFaultScope& operator=(const AllocFaultScope&) = delete;
+};
+
+// Call tracing: SHT_TRACE = 1 (read on every call) writes one line per traced entry point to
+// stderr (name, arguments, status, host time); SHT_TRACE = 2 also records events around a
+// stream call, waits for the second and adds the device time.
+class TraceCall {
+ public:
+  TraceCall(const char* name, int device, void* stream);
+  ~TraceCall();
+  TraceCall(const TraceCall&) = delete;
+  TraceCall& operator=(const TraceCall&) = delete;
+  bool on() const { return level_ > 0; }
+  void args(const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+  int done(int rc);  // logs the call and returns rc
+
+ private:
+  const char* name_;
+  int level_ = 0, device_ = -1;
+  void* stream_ = nullptr;
+  double t0_ = 0.0;
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  char args_[192] = {0};
+};
+
 }  // namespace sht
