@@ -76,6 +76,13 @@ template <> struct AFrag<P32> { float a1, a2; };  // summed at the MFMA, after t
 // and skipping the masked loads measured faster.
 template <int PREC> constexpr bool kBranchFree = PREC == P32;
 
+// Which K loop a level kernel compiles for a wave's row tiles: 0 a lone tile, 1 a pair, 2 one
+// loop that tests at run time whether the second tile exists.
+template <int V>
+struct TileCount {
+  static constexpr int value = V;
+};
+
 // Entry p[i] where ok holds, else 0 (branch-free for the precisions that ask for it).
 template <int PREC, class T>
 __device__ __forceinline__ T sel_load(const T* p, long long i, bool ok, long long safe) {
@@ -341,6 +348,11 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
     // read instead of two dependent ones
     constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
     const int nsteps = (nr + 3) >> 2;
+    // The K loop is compiled twice, for a pair of row tiles and for a lone tile, so that the
+    // pair's matrix instructions run without a branch between them.
+    auto kloop = [&](auto tiles) {
+    constexpr int TC = decltype(tiles)::value;
+    const bool TWO = TC == 2 ? two : TC == 1;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
     int roc[PF], ron[PF];
     auto fetch = [&](int s0, AFrag<PREC>* d0, AFrag<PREC>* d1, int* ro) {
@@ -350,7 +362,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const bool kin = kk < nr;
         const long long base = toff + static_cast<long long>(kk) * k;
         d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k, toff);
-        d1[u] = load_a<PREC>(fp, base + i1, kin && two && i1 < k, toff);
+        if (TWO || kBranchFree<PREC>) d1[u] = load_a<PREC>(fp, base + i1, kin && TWO && i1 < k, toff);
         ro[u] = red[kin ? kk : 0] * LD;
       }
     };
@@ -380,14 +392,13 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         for (int n = 0; n < NTL; ++n) {
           const BFrag<PREC> b = make_b<PREC>(xv[n], bsc[n]);
           acc[0][n].step(a0c[u], b);
-          // when !two the second tile's rows lie past the block and are never stored; the
-          // branch-free form computes it anyway
-          if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
+          // a lone tile's partner rows are never stored; the branch-free form computes them
+          if (kBranchFree<PREC> || TWO) acc[1][n].step(a1c[u], b);
         }
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           acc[0][n].flush_step();
-          acc[1][n].flush_step();
+          if (TWO) acc[1][n].flush_step();
         }
       }
 #pragma unroll
@@ -396,6 +407,11 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         acc[1][n].flush();
       }
     }
+    };
+    if (two)
+      kloop(TileCount<1>{});
+    else
+      kloop(TileCount<0>{});
     double* ob = out + static_cast<long long>(tk.out_row[o]) * R + c0 + lc * NTL;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -500,6 +516,12 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
     const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
     constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
     const int nsteps = (k + 3) >> 2;
+    // compiled for a pair of row tiles and for a lone tile (no branch between the pair's
+    // matrix instructions), as in the synthesis kernel; FP64 keeps one loop with the test at
+    // run time, which measured faster for it (1.4 ms per step at l = 1024, 64 fields)
+    auto kloop = [&](auto tiles) {
+    constexpr int TC = decltype(tiles)::value;
+    const bool TWO = TC == 2 ? two : TC == 1;
     AFrag<PREC> a0c[PF], a1c[PF], a0n[PF], a1n[PF];
     constexpr int PB = WLDS ? 1 : PF;  // B fragments prefetched with A when read from global
     double bc[PB][NTL], bn[PB][NTL];
@@ -510,7 +532,7 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const bool iin = i < k;
         const long long base = toff + static_cast<long long>(i) * nr;
         d0[u] = load_a<PREC>(fp, base + j0, iin && j0 < nr, toff);
-        d1[u] = load_a<PREC>(fp, base + j1, iin && two && j1 < nr, toff);
+        if (TWO || kBranchFree<PREC>) d1[u] = load_a<PREC>(fp, base + j1, iin && TWO && j1 < nr, toff);
         if (!WLDS)  // (branch-free: row 0 stands in for rows past the block)
           load_cols<NTL, PREC>(wg + static_cast<long long>(kBranchFree<PREC> && !iin ? 0 : i) * R + lc * NTL, iin,
                                b[u % PB]);
@@ -541,12 +563,12 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         for (int n = 0; n < NTL; ++n) {
           const BFrag<PREC> b = make_b<PREC>(WLDS ? xv[n] : bc[u % PB][n], bsc[n]);
           acc[0][n].step(a0c[u], b);
-          if (kBranchFree<PREC> || two) acc[1][n].step(a1c[u], b);
+          if (kBranchFree<PREC> || TWO) acc[1][n].step(a1c[u], b);
         }
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           acc[0][n].flush_step();
-          acc[1][n].flush_step();
+          if (TWO) acc[1][n].flush_step();
         }
       }
 #pragma unroll
@@ -554,6 +576,15 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
         acc[0][n].flush();
         acc[1][n].flush();
       }
+    }
+    };
+    if constexpr (PREC == P64) {
+      kloop(TileCount<2>{});
+    } else {
+      if (two)
+        kloop(TileCount<1>{});
+      else
+        kloop(TileCount<0>{});
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
