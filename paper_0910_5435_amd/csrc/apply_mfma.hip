@@ -839,7 +839,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
     }
     // Two output tiles per pass through the rows, so that one tile's matrix instructions
     // overlap the other's accumulator hand-over (the split form flushes after every K-step);
-    // a tile past the last one repeats the last one's operands and is not stored.
+    // a wave's last tile, when it has no partner, runs a loop of its own.
 #pragma unroll
     for (int u = 0; u < MAXT; u += 2) {
       const int q0 = t0 + wave + 4 * u;  // tile index over [output 0 tiles | output 1 tiles]
@@ -859,47 +859,55 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
       }
       constexpr int PF = PIN ? kPrefetch / 2 : kPrefetch / 4;
       const int nsteps = (ih + 3) >> 2;
-      AFrag<PREC> ac0[PF], an0[PF], ac1[PF], an1[PF];
-      auto fetch = [&](int s0) {
+      auto kloop = [&](auto tiles) __attribute__((always_inline)) {
+        constexpr bool TWO = decltype(tiles)::value == 1;
+        AFrag<PREC> ac0[PF], an0[PF], ac1[PF], an1[PF];
+        auto fetch = [&](int s0) {
 #pragma unroll
-        for (int w = 0; w < PF; ++w) {
-          const int i = (s0 + w) * 4 + lr;
-          an0[w] = load_a<PREC>(fp, so0 + static_cast<long long>(i0 + i) * kk0 + a0, i < ih && a0 < kk0, so0);
-          an1[w] = load_a<PREC>(fp, so1 + static_cast<long long>(i0 + i) * kk1 + a1, i < ih && a1 < kk1, so1);
+          for (int w = 0; w < PF; ++w) {
+            const int i = (s0 + w) * 4 + lr;
+            an0[w] = load_a<PREC>(fp, so0 + static_cast<long long>(i0 + i) * kk0 + a0, i < ih && a0 < kk0, so0);
+            if (TWO)
+              an1[w] = load_a<PREC>(fp, so1 + static_cast<long long>(i0 + i) * kk1 + a1, i < ih && a1 < kk1, so1);
+          }
+        };
+        if (nsteps > 0) fetch(0);
+        for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
+#pragma unroll
+          for (int w = 0; w < PF; ++w) {
+            ac0[w] = an0[w];
+            if (TWO) ac1[w] = an1[w];
+          }
+          if (s0 + PF < nsteps) fetch(s0 + PF);
+          if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+#pragma unroll
+          for (int w = 0; w < PF; ++w) {
+            const int i = (s0 + w) * 4 + lr;
+            const bool iin = i < ih;
+            const double* e0 = src0 + (iin ? i : 0) * LD + lc * NTL;
+            const double* e1 = src1 + (iin ? i : 0) * LD + lc * NTL;
+#pragma unroll
+            for (int n = 0; n < NTL; ++n) {
+              acc[u][n].step(ac0[w], b_from<PREC>(e0, n, iin, bs0[n]));
+              if (TWO) acc[u + 1][n].step(ac1[w], b_from<PREC>(e1, n, iin, bs1[n]));
+            }
+#pragma unroll
+            for (int n = 0; n < NTL; ++n) {
+              acc[u][n].flush_step();
+              if (TWO) acc[u + 1][n].flush_step();
+            }
+          }
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) {
+            acc[u][n].flush();
+            if (TWO) acc[u + 1][n].flush();
+          }
         }
       };
-      if (nsteps > 0) fetch(0);
-      for (int s0 = 0; s0 < nsteps; s0 += PF) {  // (the block hand-over of the level loops)
-#pragma unroll
-        for (int w = 0; w < PF; ++w) {
-          ac0[w] = an0[w];
-          ac1[w] = an1[w];
-        }
-        if (s0 + PF < nsteps) fetch(s0 + PF);
-        if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
-#pragma unroll
-        for (int w = 0; w < PF; ++w) {
-          const int i = (s0 + w) * 4 + lr;
-          const bool iin = i < ih;
-          const double* e0 = src0 + (iin ? i : 0) * LD + lc * NTL;
-          const double* e1 = src1 + (iin ? i : 0) * LD + lc * NTL;
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) {
-            acc[u][n].step(ac0[w], b_from<PREC>(e0, n, iin, bs0[n]));
-            acc[u + 1][n].step(ac1[w], b_from<PREC>(e1, n, iin, bs1[n]));
-          }
-#pragma unroll
-          for (int n = 0; n < NTL; ++n) {
-            acc[u][n].flush_step();
-            acc[u + 1][n].flush_step();
-          }
-        }
-#pragma unroll
-        for (int n = 0; n < NTL; ++n) {
-          acc[u][n].flush();
-          acc[u + 1][n].flush();
-        }
-      }
+      if (q1 != q0)
+        kloop(TileCount<1>{});
+      else
+        kloop(TileCount<0>{});
     }
   }
 #pragma unroll
