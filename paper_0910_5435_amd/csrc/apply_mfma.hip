@@ -284,7 +284,8 @@ __device__ void column_scales(int rows, Fetch&& fetch, double* red, int* sc) {
 
 // ------------------------------------------------------------------- level, synthesis
 // One (task, column block): out_o = in[skel_o] + T_o in[red_o] for the task's outputs.  The
-// input block is staged in `lds` (K x (NT + 2) doubles, then the index lists).
+// input block is staged in `lds` (K x (NT + 2) doubles, one row of zeros, then the index
+// lists).
 template <int NT, int PREC, bool PIN = true>
 __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
                                  const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
@@ -296,9 +297,11 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
   __shared__ int colsc[NT];
   const int K = tk.K;
   const long long c0 = static_cast<long long>(blk) * NT;
-  double* xs = lds;                                          // K x LD
-  uint16_t* ix = reinterpret_cast<uint16_t*>(lds + K * LD);  // [skel0 red0 skel1 red1]
+  double* xs = lds;                                                // K x LD, then row K = 0
+  uint16_t* ix = reinterpret_cast<uint16_t*>(lds + (K + 1) * LD);  // [skel0 red0 skel1 red1]
   const int k0 = tk.k[0], k1 = tk.k[1] < 0 ? 0 : tk.k[1];
+  // the zero row: the B operand of K-steps past the end of the contraction (no per-step mask)
+  for (int c = threadIdx.x; c < LD; c += 256) xs[K * LD + c] = 0.0;
   if (io.on() && tk.mp >= 0) {
     const PairDesc pd = pairs[tk.mp];
     gather_leaf_block<NT, LD>(io, pd.m, pd.p, tk.in_row - pd.in_base, K, c0, xs);
@@ -363,7 +366,7 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
         const long long base = toff + static_cast<long long>(kk) * k;
         d0[u] = load_a<PREC>(fp, base + i0, kin && i0 < k, toff);
         if (TWO || kBranchFree<PREC>) d1[u] = load_a<PREC>(fp, base + i1, kin && TWO && i1 < k, toff);
-        ro[u] = red[kin ? kk : 0] * LD;
+        ro[u] = (kin ? red[kk] : K) * LD;
       }
     };
     // Each block's fragments are taken over at the top of the loop (the only wait on their
@@ -382,12 +385,13 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
       }
       if (s0 + PF < nsteps) fetch(s0 + PF, a0n, a1n, ron);
       if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
+      // the vector rows are read one K-step ahead (steps past the end read the zero row)
+      double xb[2][NTL];
+      load_cols<NTL, PREC>(xs + roc[0] + lc * NTL, true, xb[0]);
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
-        const int kk = (s0 + u) * 4 + lr;
-        const bool kin = kk < nr;
-        double xv[NTL];
-        load_cols<NTL, PREC>(xs + roc[u] + lc * NTL, kin, xv);
+        if (u + 1 < PF) load_cols<NTL, PREC>(xs + roc[u + 1] + lc * NTL, true, xb[(u + 1) & 1]);
+        const double* xv = xb[u & 1];
 #pragma unroll
         for (int n = 0; n < NTL; ++n) {
           const BFrag<PREC> b = make_b<PREC>(xv[n], bsc[n]);
@@ -1025,10 +1029,10 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
     if (wlds) rows = rw;
   }
   const int NT = (PREC != PSPLIT && R % 32 == 0 && rows * 34 * 8 <= tile32_lds_budget()) ? 32 : 16;
-  if (rows * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
+  if ((rows + 1) * 18 * 8 + 4LL * K + 16 > 150 * 1024) return hipErrorInvalidConfiguration;
   const int nblk = R / NT;
   const dim3 grid(xcd_grid(cnt, nblk));
-  const size_t lds = static_cast<size_t>(rows) * (NT + 2) * 8 + 4 * static_cast<size_t>(K) + 16;
+  const size_t lds = static_cast<size_t>(rows + 1) * (NT + 2) * 8 + 4 * static_cast<size_t>(K) + 16;
   const FacPtr fp = fac_ptr(P, transpose);
   hipError_t e;
 #define LEVEL_LAUNCH(KER)                                                                              \

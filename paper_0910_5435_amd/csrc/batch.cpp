@@ -118,7 +118,7 @@ size_t group_lds(const sht_plan_s* P, int nt, bool trans, int precision) {
   for (int v : P->step_maxK) maxK = std::max(maxK, v);
   (void)precision;  // transposed level items read their output vectors from global memory
   const size_t rows = static_cast<size_t>(maxK);
-  size_t lds = rows * (nt + 2) * 8 + 4 * static_cast<size_t>(maxK) + 16;
+  size_t lds = (rows + 1) * (nt + 2) * 8 + 4 * static_cast<size_t>(maxK) + 16;  // + the zero row
   if (trans)
     lds = std::max(lds, final_trans_lds_bytes());
   else
