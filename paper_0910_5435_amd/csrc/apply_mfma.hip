@@ -884,16 +884,27 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
           }
           if (s0 + PF < nsteps) fetch(s0 + PF);
           if (PIN) __builtin_amdgcn_sched_barrier(0);  // the next block's loads stay where they are issued
-#pragma unroll
-          for (int w = 0; w < PF; ++w) {
+          // the folded rows are read from LDS one K-step ahead
+          BFrag<PREC> bb[2][2][NTL];
+          auto read_b = [&](int w, BFrag<PREC> (&b0)[NTL], BFrag<PREC> (&b1)[NTL]) {
             const int i = (s0 + w) * 4 + lr;
             const bool iin = i < ih;
             const double* e0 = src0 + (iin ? i : 0) * LD + lc * NTL;
             const double* e1 = src1 + (iin ? i : 0) * LD + lc * NTL;
 #pragma unroll
             for (int n = 0; n < NTL; ++n) {
-              acc[u][n].step(ac0[w], b_from<PREC>(e0, n, iin, bs0[n]));
-              if (TWO) acc[u + 1][n].step(ac1[w], b_from<PREC>(e1, n, iin, bs1[n]));
+              b0[n] = b_from<PREC>(e0, n, iin, bs0[n]);
+              if (TWO) b1[n] = b_from<PREC>(e1, n, iin, bs1[n]);
+            }
+          };
+          read_b(0, bb[0][0], bb[0][1]);
+#pragma unroll
+          for (int w = 0; w < PF; ++w) {
+            if (w + 1 < PF) read_b(w + 1, bb[(w + 1) & 1][0], bb[(w + 1) & 1][1]);
+#pragma unroll
+            for (int n = 0; n < NTL; ++n) {
+              acc[u][n].step(ac0[w], bb[w & 1][0][n]);
+              if (TWO) acc[u + 1][n].step(ac1[w], bb[w & 1][1][n]);
             }
 #pragma unroll
             for (int n = 0; n < NTL; ++n) {
