@@ -955,7 +955,10 @@ k_final_trans_mfma(const FinalTask* __restrict__ tasks, long long ntasks, int nb
   long long ti;
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
-  final_trans_body<NT, ICH, PREC>(tasks[ti], blk, fp, Yin, scale, half, v0buf, v1buf, l, R, lds);
+  // output tiles per wave and pass: fewer accumulators, more resident waves (split: two tiles,
+  // 128 VGPRs, four waves per SIMD; FP64: four tiles, 124 VGPRs); larger ranks take more passes
+  final_trans_body<NT, ICH, PREC, true, (PREC == PSPLIT ? 2 : 4)>(tasks[ti], blk, fp, Yin, scale, half, v0buf,
+                                                                   v1buf, l, R, lds);
 }
 
 // ------------------------------------------------------------------ factor preparation
