@@ -349,7 +349,9 @@ __device__ void level_synth_body(const LevelTask& tk, int blk, const FacPtr& fp,
     // factor fragments are fetched PF K-steps ahead (double-buffered in registers), and with
     // them the LDS row offsets of the gathered vector rows, so that a K-step waits on one LDS
     // read instead of two dependent ones
-    constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
+    // K-steps fetched ahead: the persistent kernel and the split form take half (fewer
+    // registers: the split 16-column kernel fits five waves per SIMD, which measured faster)
+    constexpr int PF = (PIN && PREC != PSPLIT) ? kPrefetch : kPrefetch / 2;
     const int nsteps = (nr + 3) >> 2;
     // The K loop is compiled twice, for a pair of row tiles and for a lone tile, so that the
     // pair's matrix instructions run without a branch between them.
@@ -518,7 +520,9 @@ __device__ void level_trans_body(const LevelTask& tk, int blk, const FacPtr& fp,
 #pragma unroll
       for (int n = 0; n < NTL; ++n) acc[u][n].zero();
     const int j0 = mt0 * 16 + lc, j1 = j0 + 16;
-    constexpr int PF = PIN ? kPrefetch : kPrefetch / 2;  // (the persistent kernel: fewer registers)
+    // K-steps fetched ahead: half in the persistent kernel and in the split form that reads its
+    // vectors from global memory (fewer registers, four waves per SIMD)
+    constexpr int PF = (PIN && (WLDS || PREC != PSPLIT)) ? kPrefetch : kPrefetch / 2;
     const int nsteps = (k + 3) >> 2;
     // compiled for a pair of row tiles and for a lone tile (no branch between the pair's
     // matrix instructions), as in the synthesis kernel; FP64 keeps one loop with the test at
