@@ -1012,12 +1012,14 @@ long long tile32_lds_budget() {
 }
 
 // Largest LDS block (bytes) for which the transposed split levels stage their output vectors
-// in LDS (two work-groups per compute unit); SHT_SPLIT_WLDS_KB overrides it (tuning).
+// in LDS; 0 by default: the form that reads them from global memory (97 VGPRs, a small LDS
+// block, four waves per SIMD) measured faster for every size class.  SHT_SPLIT_WLDS_KB
+// (tuning) sets a positive cap in KiB.
 long long split_wlds_cap() {
   static const long long v = [] {
     const char* e = std::getenv("SHT_SPLIT_WLDS_KB");
-    const long long kb = e ? std::atoll(e) : 76;
-    return (kb > 0 ? kb : 76) * 1024;
+    const long long kb = e ? std::atoll(e) : 0;
+    return (kb > 0 ? kb : 0) * 1024;
   }();
   return v;
 }
@@ -1034,10 +1036,10 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
   const LevelTask* tasks = P->d.tasks + P->step_off[step] + lc.off;
   const int K = lc.maxK;
   // LDS holds the task's K x NT input block: 32 columns while that stays within the tile
-  // budget.  The split form always takes 16 columns: its 16-column kernels fit three waves
+  // budget.  The split form always takes 16 columns: its 16-column kernels fit more waves
   // per SIMD in registers, which measured faster than the halved factor reads of 32 (FP64
-  // measured the other way).  The transposed split form also stages both output blocks,
-  // unless that block would exceed split_wlds_cap() (then the vectors are read from global
+  // measured the other way).  The transposed split form stages both output blocks only
+  // where split_wlds_cap() allows (by default nowhere: the vectors are read from global
   // memory).
   bool wlds = false;
   long long rows = K;

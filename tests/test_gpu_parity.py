@@ -348,3 +348,40 @@ def test_dense_q_export_matches_oracle():
         n = ref.shape[1]
         np.testing.assert_allclose(Qh[mp][:n].T, ref, rtol=0, atol=2e-14)
         assert np.all(Qh[mp][n:] == 0)
+
+
+_STAGED_SCRIPT = r"""
+import sys
+import numpy as np
+import torch
+import sht_synthetic as syn
+from paper_0910_5435_amd import Plan
+
+l, C, F = 256, 64, 16
+P = Plan(l, eps=1e-12, leaf_width=C, precision="split32")
+grid = torch.from_numpy(syn.grid(l, F, seed=21)).to("cuda")
+np.save(sys.argv[1], P.analyze(grid, precision="split32").cpu().numpy())
+"""
+
+
+def test_split_staged_vectors_match_global_reads(tmp_path):
+    # the split transposed levels read their vectors from global memory by default; the
+    # staged form (SHT_SPLIT_WLDS_KB, read once per process, so it runs in a child process)
+    # adds the same terms in an order that cannot change the result: bit-identical output
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = {}
+    for cap in ("0", "76"):
+        env = dict(os.environ, SHT_SPLIT_WLDS_KB=cap, PYTHONPATH=root)
+        path = tmp_path / f"a{cap}.npy"
+        r = subprocess.run([sys.executable, "-c", _STAGED_SCRIPT, str(path)], env=env, cwd=root,
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs[cap] = np.load(path)
+    assert np.array_equal(outs["0"], outs["76"])
+    l, F = 256, 16
+    ref = oracle.analyze(syn.grid(l, F, seed=21), l)
+    assert _rel(outs["0"], ref).max() < SPLIT_TOL
