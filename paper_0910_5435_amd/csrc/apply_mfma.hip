@@ -445,6 +445,18 @@ k_level_synth_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   level_synth_body<NT, PREC>(tasks[ti], blk, fp, idx, pairs, in, out, R, io, lds);
 }
 
+// The split 16-column form held to six waves per SIMD (80 VGPRs).
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(6, 8)))
+k_level_synth_split6(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                     const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                     const double* __restrict__ in, double* __restrict__ out, int R, CoefIO io) {
+  extern __shared__ double lds[];
+  long long ti;
+  int blk;
+  if (!xcd_map(ntasks, nblk, ti, blk)) return;
+  level_synth_body<16, PSPLIT>(tasks[ti], blk, fp, idx, pairs, in, out, R, io, lds);
+}
+
 // ------------------------------------------------------------------ level, transposed
 // Output block o contributes T_o^T w_o at rows red_o and w_o at rows skel_o; every input row
 // gets exactly one term from each block.  Both blocks run at once (their row-tile pairs are
@@ -651,6 +663,19 @@ k_level_trans_mfma(const LevelTask* __restrict__ tasks, long long ntasks, int nb
   int blk;
   if (!xcd_map(ntasks, nblk, ti, blk)) return;
   level_trans_body<NT, PREC, WLDS>(tasks[ti], blk, fp, idx, pairs, win, xout, R, io, lds);
+}
+
+// The split form with vectors read from global memory, held to 96 VGPRs (one fewer than it
+// takes unconstrained): five waves per SIMD where the LDS block allows five work-groups.
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(5, 8)))
+k_level_trans_split_g(const LevelTask* __restrict__ tasks, long long ntasks, int nblk, FacPtr fp,
+                      const uint16_t* __restrict__ idx, const PairDesc* __restrict__ pairs,
+                      const double* __restrict__ win, double* __restrict__ xout, int R, CoefIO io) {
+  extern __shared__ double lds[];
+  long long ti;
+  int blk;
+  if (!xcd_map(ntasks, nblk, ti, blk)) return;
+  level_trans_body<16, PSPLIT, false>(tasks[ti], blk, fp, idx, pairs, win, xout, R, io, lds);
 }
 
 // ------------------------------------------------------------------- final, synthesis
@@ -1065,9 +1090,15 @@ hipError_t level_class(const sht_plan_s* P, int step, const LaunchClass& lc, boo
     if (NT == 32)
       LEVEL_LAUNCH((k_level_synth_mfma<32, PREC>));
     else
-      LEVEL_LAUNCH((k_level_synth_mfma<16, PREC>));
+      if constexpr (PREC == PSPLIT)
+        LEVEL_LAUNCH(k_level_synth_split6);
+      else
+        LEVEL_LAUNCH((k_level_synth_mfma<16, PREC>));
   } else if (PREC == PSPLIT && !wlds) {
-    LEVEL_LAUNCH((k_level_trans_mfma<16, PREC, false>));
+    if constexpr (PREC == PSPLIT)
+      LEVEL_LAUNCH(k_level_trans_split_g);
+    else
+      LEVEL_LAUNCH((k_level_trans_mfma<16, PREC, false>));
   } else {
     if (NT == 32)
       LEVEL_LAUNCH((k_level_trans_mfma<32, PREC>));
