@@ -814,7 +814,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
                                  int l, int R, double* lds) {
   constexpr int NTL = NT / 16;
   constexpr int LD = ldp<NT>();
-  // MAXT: output tiles per wave and pass (a pass covers 4 MAXT tiles; 6: 384 rows); even
+  // MAXT: output tiles per wave and pass (a pass covers 4 MAXT tiles, 64 MAXT rows); even
   static_assert(MAXT % 2 == 0, "output tiles go through the rows in pairs");
   double* eo[2] = {lds, lds + ICH * LD};
   __shared__ double red_s[256];
@@ -827,7 +827,8 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   const int lc = lane & 15, lr = lane >> 4;
   const int nm0 = (k0 + 15) >> 4, nm1 = (k1 + 15) >> 4;
   // Output tiles [0, nm0 + nm1) are covered in passes of 4 MAXT tiles (the accumulators one
-  // wave keeps in registers); ranks k0 + k1 above 384 take more than one pass over the rows.
+  // wave keeps in registers); ranks k0 + k1 above 64 MAXT take more than one pass over the
+  // rows, each staging the folded rows again.
   for (int t0 = 0; t0 < nm0 + nm1; t0 += 4 * MAXT) {
   Acc<PREC> acc[MAXT][NTL];
 #pragma unroll
@@ -839,7 +840,7 @@ __device__ void final_trans_body(const FinalTask& ft, int blk, const FacPtr& fp,
   for (int i0 = 0; i0 < h; i0 += ICH) {
     const int ih = min(ICH, h - i0);
     __syncthreads();
-    // two items in flight: this kernel keeps up to 24 accumulator tiles per wave in registers
+    // two items in flight: the accumulator tiles of the pass stay live in registers meanwhile
     staged<double2, 2>(
         ih * NT,
         [&](int e) {
