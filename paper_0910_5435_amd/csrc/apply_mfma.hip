@@ -1038,9 +1038,9 @@ long long tile32_lds_budget() {
 }
 
 // Largest LDS block (bytes) for which the transposed split levels stage their output vectors
-// in LDS; 0 by default: the form that reads them from global memory (97 VGPRs, a small LDS
-// block, four waves per SIMD) measured faster for every size class.  SHT_SPLIT_WLDS_KB
-// (tuning) sets a positive cap in KiB.
+// in LDS; 0 by default: the form that reads them from global memory (k_level_trans_split_g:
+// 96 VGPRs and a small LDS block, five waves per SIMD) measured faster for every size class.
+// SHT_SPLIT_WLDS_KB (tuning) sets a positive cap in KiB.
 long long split_wlds_cap() {
   static const long long v = [] {
     const char* e = std::getenv("SHT_SPLIT_WLDS_KB");
